@@ -1,0 +1,229 @@
+/*
+ * ircur.h -- C ABI of libircur, IRCUR (Iterated Robust CUR) for robust PCA on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Cai, Hamm, Huang, Li, Wang, "Rapid Robust Principal Component
+ * Analysis: CUR Accelerated Inexact Low Rank Estimation" (arXiv 2010.07422).
+ * Given D = L + S (rank(L) <= r, S sparse; problem (1)), Algorithm 1 alternates
+ *   Phase I  (section 3.2): [S_{k+1}] = T_zeta[D - L_k] on sampled rows I and
+ *            columns J, with the hard threshold T_zeta of eq. (4) and the
+ *            sampled low-rank estimate of eq. (5);
+ *   Phase II (section 3.1): C = [D-S]_{:,J}, U = H_r([D-S]_{I,J}),
+ *            R = [D-S]_{I,:} (eq. (2)) and L_{k+1} = C U^+ R (eq. (3)),
+ * until the sampled residual e_k of eq. (6) is <= eps.  L is never formed:
+ * the library keeps L_k = A_k B_k with A_k = C V_r Sigma_r^+ (n1 x r) and
+ * B_k = W_r^T R (r x n2), where U = W_r Sigma_r V_r^T.
+ *
+ * Conventions
+ *   - All functions are extern "C", return an int status (ircur_status), never
+ *     throw, and validate every argument on the host before touching the GPU;
+ *     an invalid argument returns IRCUR_ERR_ARG with no side effects.
+ *   - "dev" pointers are HIP device pointers on the context's device; "host"
+ *     pointers are ordinary host memory.  Matrices are row-major.
+ *   - D (and its transpose, if given) is BORROWED: caller-owned device memory
+ *     that must stay valid and unchanged until ircur_destroy.  The context and
+ *     its workspace are owned by the library.
+ *   - Work is enqueued on the stream given to ircur_init (a hipStream_t; NULL
+ *     is the null stream).  Functions that return host values synchronise
+ *     that stream; those that only fill device buffers do not.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Factor dtype: double when dtype == IRCUR_F64, float otherwise.
+ */
+#ifndef IRCUR_H
+#define IRCUR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ircur_ctx ircur_ctx;
+
+enum ircur_status {
+    IRCUR_OK = 0,
+    IRCUR_NOT_CONVERGED = 1,        /* max_iter reached with e > eps (result valid) */
+    IRCUR_WARN_RANK_DEFICIENT = 2,  /* a kept-rank test dropped components of U^+ */
+    IRCUR_WARN_SVD_INEXACT = 3,     /* top-r SVD hit its iteration cap (sigma_r ~ sigma_{r+1}) */
+    IRCUR_ERR_ARG = -1,
+    IRCUR_ERR_ALLOC = -2,
+    IRCUR_ERR_DEVICE = -3,          /* HIP error, or no usable device */
+    IRCUR_ERR_SVD = -4,
+    IRCUR_ERR_NONFINITE = -5,       /* NaN/Inf met in D or in the iterates */
+    IRCUR_ERR_STATE = -6,           /* call not valid in the current state */
+    IRCUR_ERR_UNSUPPORTED = -7      /* sizes beyond a documented kernel limit */
+};
+
+enum ircur_dtype { IRCUR_F64 = 0, IRCUR_F32 = 1, IRCUR_BF16 = 2 };
+
+/* Largest supported rank r (the factor kernels are compiled for padded ranks). */
+#define IRCUR_MAX_RANK 32
+
+/*
+ * Parameters of Algorithm 1 (its inputs: D, r, eps, zeta_0, gamma, |I|, |J|)
+ * plus the implementation choices the paper leaves open.
+ */
+typedef struct {
+    int64_t n1, n2;      /* D is n1 x n2 (n1, n2 >= 1)                              */
+    int64_t ldD;         /* row stride of D in elements, ldD >= n2                  */
+    int32_t r;           /* target rank, 1 <= r <= min(sI, sJ, IRCUR_MAX_RANK)      */
+    int32_t sI, sJ;      /* |I| <= n1, |J| <= n2 (section 3.5: c r log n)            */
+    int32_t dtype;       /* ircur_dtype of D: F64 computes in double; F32 and BF16
+                            compute in float; the SVD of U is always double        */
+    int32_t resample;    /* 1: IRCUR-R (new I, J every iteration), 0: IRCUR-F (3.4) */
+    int32_t err_mode;    /* 0: e_k of eq. (6) read literally, with L_{k+1}, S_{k+1}
+                            on the iteration's own I, J; 1: the below-threshold part
+                            of D - L_k on the new I, J                            */
+    double  zeta0;       /* initial threshold zeta_0 > 0 (0 allowed: removes all)  */
+    double  gamma;       /* decay, zeta_{k+1} = gamma^k zeta_0, 0 < gamma <= 1      */
+    double  eps;         /* stop when e_k <= eps                                    */
+    int32_t max_iter;    /* iteration cap, >= 1                                     */
+    uint64_t seed;       /* index-sampler seed (SplitMix64 stream, see below)       */
+    double  svd_tol;     /* relative residual tolerance of the top-r SVD; 0: default
+                            (1e-12 for F64, 1e-9 otherwise)                        */
+    int32_t svd_max_it;  /* subspace-iteration cap of the top-r SVD; 0: default 64   */
+    int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default       */
+} ircur_params;
+
+/* Fill *p with defaults (gamma 0.7, eps 1e-5, max_iter 100, resample 1,
+ * err_mode 0, dtype F64, everything else 0).  Sizes must still be set. */
+int ircur_params_default(ircur_params* p);
+
+/*
+ * Create a context for D (device, dtype p->dtype, n1 x n2, row stride p->ldD).
+ * Dt: optional device copy of D^T (n2 x n1, row stride ldDt >= n1, same dtype);
+ * if NULL the library builds one (a transpose kernel; n1*n2 elements of
+ * workspace).  The context starts at k = 0 with L_0 = S_0 = 0 (Algorithm 1).
+ * stream: hipStream_t to enqueue on, or NULL.
+ * Errors: IRCUR_ERR_ARG (any invalid size, pointer or parameter),
+ * IRCUR_ERR_UNSUPPORTED (sizes beyond a kernel limit), IRCUR_ERR_DEVICE,
+ * IRCUR_ERR_ALLOC.  On error *out is set to NULL.
+ */
+int ircur_init(ircur_ctx** out, const ircur_params* p, const void* D_dev,
+               const void* Dt_dev, int64_t ldDt, void* stream);
+
+/*
+ * One iteration k -> k+1 of Algorithm 1 (Phase I, Phase II, e_{k+1}).
+ * I_host, J_host: optional host arrays of sI / sJ distinct indices (any
+ * order; they are sorted internally); if NULL the library's sampler draws
+ * them (stream 0 for IRCUR-F, stream k for IRCUR-R).  Synchronises and writes
+ * e_{k+1} to *e_out (may be NULL).  Returns IRCUR_ERR_STATE if the context has
+ * already stopped (e <= eps or max_iter reached) unless ircur_reset was called.
+ */
+int ircur_step(ircur_ctx* ctx, const int32_t* I_host, const int32_t* J_host,
+               double* e_out);
+
+/*
+ * Enqueue up to n_iter iterations with sampled index sets, without waiting.
+ * A device-side stop flag turns the remaining launches into no-ops once
+ * e <= eps or k = max_iter.  Use ircur_sync to read the outcome.
+ */
+int ircur_enqueue(ircur_ctx* ctx, int32_t n_iter);
+
+/* Wait for enqueued work; report iterations done so far and the last e. */
+int ircur_sync(ircur_ctx* ctx, int32_t* k_out, double* e_out);
+
+/*
+ * Run Algorithm 1 to the stop rule (e_k <= eps) or max_iter.  Writes the
+ * number of iterations and the last e.  Returns IRCUR_OK or
+ * IRCUR_NOT_CONVERGED (both with a valid result), or an error.
+ */
+int ircur_solve(ircur_ctx* ctx, int32_t* iters_out, double* e_out);
+
+/* Forget the stop state and restart from L_0 = 0, k = 0 (same D, params). */
+int ircur_reset(ircur_ctx* ctx);
+
+/*
+ * Copy the current factors (L_k = A_k B_k): At_dev receives A_k^T (r x n1),
+ * B_dev receives B_k (r x n2), both row-major in the factor dtype.  Either
+ * pointer may be NULL.  Asynchronous on the context's stream.
+ */
+int ircur_get_factors(ircur_ctx* ctx, void* At_dev, void* B_dev);
+
+/* Overwrite the factors (same layouts) and the iteration counter k. */
+int ircur_set_factors(ircur_ctx* ctx, const void* At_dev, const void* B_dev,
+                      int32_t k);
+
+/* e_1 .. e_k of the run so far (host); *n_out = min(k, cap). Synchronises. */
+int ircur_get_history(ircur_ctx* ctx, double* e_host, int32_t cap,
+                      int32_t* n_out);
+
+/* Index sets of the last completed iteration (host, sorted). Synchronises. */
+int ircur_get_sets(ircur_ctx* ctx, int32_t* I_host, int32_t* J_host);
+
+/*
+ * Internals of the last completed iteration, for verification (device):
+ * M_dev: [D - S_{k}]_{I,J} as double (sI x sJ); W_dev (sI x r), sigma_dev (r),
+ * V_dev (sJ x r): the top-r SVD of M as double, dropped components zero.
+ * Any pointer may be NULL.  Asynchronous.
+ */
+int ircur_get_core(ircur_ctx* ctx, double* M_dev, double* W_dev,
+                   double* sigma_dev, double* V_dev);
+
+/*
+ * Output of Algorithm 1 for the last completed iteration k: C_k (n1 x sJ),
+ * U_k^+ (sJ x sI) and R_k (n1 x ... sI x n2), and optionally the sparse
+ * blocks S_I = [S_k]_{I,:} (sI x n2) and S_J = [S_k]_{:,J} (n1 x sJ), all in
+ * the factor dtype (device).  Any pointer may be NULL.  Asynchronous.
+ */
+int ircur_get_cur(ircur_ctx* ctx, void* C_dev, void* Upinv_dev, void* R_dev,
+                  void* SI_dev, void* SJ_dev);
+
+/*
+ * Algorithm 2 (CUR to SVD) applied to the current estimate L_k = A_k B_k:
+ * W_dev (n1 x r), sigma_dev (r), V_dev (n2 x r), all double, with
+ * L_k = W diag(sigma) V^T.  Asynchronous.
+ */
+int ircur_to_svd(ircur_ctx* ctx, double* W_dev, double* sigma_dev, double* V_dev);
+
+/*
+ * Full sparse part S = T_zeta(D - A_k B_k) over all of D (the video
+ * foreground), written to S_dev (n1 x n2, row stride ldS, dtype of D), with
+ * zeta <= 0 meaning the threshold of the last completed iteration.
+ * Returns the number of nonzeros in *nnz_out (may be NULL; synchronises if not).
+ */
+int ircur_sparse_full(ircur_ctx* ctx, double zeta, void* S_dev, int64_t ldS,
+                      int64_t* nnz_out);
+
+/*
+ * Checkpoint / resume.  The state is (k, stop flag, A_k, B_k, e history):
+ * ircur_get_state with buf == NULL writes the required size to *bytes.
+ * Resuming gives the same trajectory bit for bit.  Host buffers; synchronises.
+ */
+int ircur_get_state(ircur_ctx* ctx, void* buf, size_t* bytes);
+int ircur_set_state(ircur_ctx* ctx, const void* buf, size_t bytes);
+
+/*
+ * Per-kernel timing with HIP events on the context's stream (for the
+ * benchmark).  When enabled, every iteration records events around its
+ * kernels; ircur_get_timing returns the accumulated milliseconds of the
+ * core, svd, pass and finalize kernels and the number of timed iterations.
+ */
+int ircur_set_timing(ircur_ctx* ctx, int32_t enable);
+int ircur_get_timing(ircur_ctx* ctx, double* ms4, int64_t* count);
+
+/* Diagnostics of the last iteration: svd iterations, svd residual, the
+ * estimated gap sigma_{r+1}/sigma_r, kept rank.  Synchronises. */
+int ircur_get_info(ircur_ctx* ctx, int32_t* svd_iters, double* svd_resid,
+                   double* gap, int32_t* kept);
+
+/*
+ * The sampler, on the host (no device needed): index sets of stream t.
+ * Generator: SplitMix64 (Steele, Lea, Flood 2014) started from
+ * mix(seed xor ((t+1) * 0xD1B54A32D192ED03)); bounded draws by 128-bit
+ * multiply-shift; distinct sets by Floyd's algorithm; I drawn before J;
+ * both sorted ascending.  IRCUR-F uses t = 0, IRCUR-R uses t = k at
+ * iteration k+1.
+ */
+int ircur_sample(uint64_t seed, int64_t t, int64_t n1, int64_t n2, int32_t sI,
+                 int32_t sJ, int32_t* I_host, int32_t* J_host);
+
+void        ircur_destroy(ircur_ctx* ctx);
+const char* ircur_strerror(int status);
+const char* ircur_last_error(const ircur_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRCUR_H */

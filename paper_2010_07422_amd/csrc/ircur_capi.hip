@@ -1,0 +1,773 @@
+// Host runtime and C ABI of libircur (see include/ircur.h).
+//
+// One IRCUR iteration (Algorithm 1, k -> k+1) is four launches on the
+// context's stream:
+//   core      M = [D - S_{k+1}]_{I,J}                      (Phase I, eq. (4), (5))
+//   svd       top-r SVD of M, pinv rule, per-row data of the pass (Phase II)
+//   pass      B_{k+1} = W_r^T R, A_{k+1} = C V_r Sigma_r^+ and the partial
+//             sums of e_{k+1}                             (eq. (2), (3), (6))
+//   finalize  e_{k+1}, history, device-side stop flag
+// Iterations are enqueued in chunks; every kernel returns at once when the
+// stop flag is set, so the host reads back state once per chunk.
+#include "ircur_internal.h"
+#include "../../include/ircur.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ircur;
+
+// --------------------------------------------------------------- sampler ---
+// SplitMix64 (Steele, Lea, Flood 2014), Floyd's sampling, multiply-shift.
+namespace {
+
+inline uint64_t sm_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct SplitMix64 {
+    uint64_t state;
+    uint64_t next() {
+        state += 0x9E3779B97F4A7C15ull;
+        return sm_mix(state);
+    }
+    uint64_t below(uint64_t m) {   // uniform in [0, m)
+        return (uint64_t)(((unsigned __int128)next() * (unsigned __int128)m) >> 64);
+    }
+};
+
+SplitMix64 index_stream(uint64_t seed, int64_t t) {
+    const uint64_t key = seed ^ ((uint64_t)(t + 1) * 0xD1B54A32D192ED03ull);
+    return SplitMix64{sm_mix(key)};
+}
+
+// k distinct values of [0, n), ascending.  Membership via a sorted vector is
+// enough for the sizes here (k is a few hundred to a few thousand).
+void floyd(SplitMix64& g, int64_t n, int32_t k, int32_t* out) {
+    std::vector<int64_t> chosen;
+    chosen.reserve(k);
+    for (int64_t j = n - k; j < n; ++j) {
+        const int64_t t = (int64_t)g.below((uint64_t)(j + 1));
+        auto it = std::lower_bound(chosen.begin(), chosen.end(), t);
+        if (it != chosen.end() && *it == t) {
+            chosen.insert(std::lower_bound(chosen.begin(), chosen.end(), j), j);
+        } else {
+            chosen.insert(it, t);
+        }
+    }
+    for (int32_t i = 0; i < k; ++i) out[i] = (int32_t)chosen[i];
+}
+
+constexpr int kChunk = 32;        // iterations per enqueue batch
+constexpr int kRing = 2 * kChunk; // index-set slots: two batches in flight
+
+float round_down_float(double z) {
+    if (!(z < 3.4e38)) return INFINITY;
+    float f = (float)z;
+    if ((double)f > z) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- context ---
+
+struct ircur_ctx {
+    ircur_params p{};
+    int R = 0, psvd = 0, G = 0, bs = 0;
+    size_t svd_lds = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    const void* D = nullptr;
+    const void* Dt = nullptr;
+    int64_t ldDt = 0;
+    void* Dt_own = nullptr;
+    size_t esz = 0, fsz = 0;
+    void* At[2] = {nullptr, nullptr};
+    void* B[2] = {nullptr, nullptr};
+    int32_t* Idev = nullptr;
+    int32_t* Jdev = nullptr;
+    int32_t* Ipin = nullptr;
+    int32_t* Jpin = nullptr;
+    double* M = nullptr;
+    double* Zp = nullptr;
+    double* Gp = nullptr;
+    double* Tp = nullptr;
+    double* prevV = nullptr;
+    double* W = nullptr;
+    double* V = nullptr;
+    double* sigma = nullptr;
+    void* rowI = nullptr;
+    void* rowJ = nullptr;
+    void* GmI = nullptr;
+    void* GmJ = nullptr;
+    void* scaleJ = nullptr;
+    double* part_row = nullptr;
+    double* part_col = nullptr;
+    int nwg_row = 0, nwg_col = 0;
+    DevState* st = nullptr;
+    DevState* st_host = nullptr;   // pinned
+    SvdInfo* info = nullptr;       // max_iter records
+    double* hist = nullptr;        // max_iter
+    int32_t k = 0;                 // completed iterations (host view after sync)
+    int32_t k_enq = 0;             // next iteration to enqueue
+    int32_t batch = 0;             // batches enqueued (selects the ring half)
+    bool stopped = false;
+    hipEvent_t h2d[2] = {nullptr, nullptr};
+    bool h2d_pending[2] = {false, false};
+    int32_t acc_next = 0;          // next iteration whose timing is not yet summed
+    std::vector<int32_t> setsI, setsJ;   // per iteration, host copy
+    std::vector<int32_t> lastJ;          // J of the previous svd (warm start)
+    bool have_prevV = false;
+    bool timing = false;
+    hipEvent_t ev[kRing][5];
+    bool ev_made = false;
+    double tsum[4] = {0, 0, 0, 0};
+    int64_t tcount = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(ircur_ctx* c, int code, const char* msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, x)                                                        \
+    do {                                                                      \
+        hipError_t e_ = (x);                                                  \
+        if (e_ != hipSuccess) {                                               \
+            if (ctx) (ctx)->err = std::string(#x) + ": " + hipGetErrorString(e_); \
+            return IRCUR_ERR_DEVICE;                                          \
+        }                                                                     \
+    } while (0)
+
+int validate(const ircur_params* p, const void* D, const void* Dt, int64_t ldDt) {
+    if (!p || !D) return IRCUR_ERR_ARG;
+    if (p->n1 < 1 || p->n2 < 1 || p->n1 > INT32_MAX || p->n2 > INT32_MAX) return IRCUR_ERR_ARG;
+    if (p->ldD < p->n2) return IRCUR_ERR_ARG;
+    if (p->sI < 1 || p->sJ < 1 || p->sI > p->n1 || p->sJ > p->n2) return IRCUR_ERR_ARG;
+    if (p->r < 1 || p->r > IRCUR_MAX_RANK || p->r > p->sI || p->r > p->sJ) return IRCUR_ERR_ARG;
+    if (p->dtype < 0 || p->dtype > 2) return IRCUR_ERR_ARG;
+    if (p->resample != 0 && p->resample != 1) return IRCUR_ERR_ARG;
+    if (p->err_mode != 0 && p->err_mode != 1) return IRCUR_ERR_ARG;
+    if (!(p->zeta0 >= 0.0) || std::isnan(p->zeta0)) return IRCUR_ERR_ARG;
+    if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return IRCUR_ERR_ARG;
+    if (!(p->eps >= 0.0)) return IRCUR_ERR_ARG;
+    if (p->max_iter < 1) return IRCUR_ERR_ARG;
+    if (!(p->svd_tol >= 0.0) || p->svd_max_it < 0) return IRCUR_ERR_ARG;
+    if (p->svd_block != 0 &&
+        (p->svd_block < p->r || p->svd_block > 32 || p->svd_block > p->sI || p->svd_block > p->sJ))
+        return IRCUR_ERR_ARG;
+    if (Dt && ldDt < p->n1) return IRCUR_ERR_ARG;
+    return IRCUR_OK;
+}
+
+template <typename T>
+int dalloc(ircur_ctx* c, T** ptr, size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        *ptr = nullptr;
+        c->err = "hipMalloc failed";
+        return IRCUR_ERR_ALLOC;
+    }
+    *ptr = (T*)q;
+    return IRCUR_OK;
+}
+
+int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+        *ptr = nullptr;
+        c->err = "hipMalloc failed";
+        return IRCUR_ERR_ALLOC;
+    }
+    return IRCUR_OK;
+}
+
+void free_all(ircur_ctx* c) {
+    void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
+                    c->M, c->Zp, c->Gp, c->Tp, c->prevV, c->W, c->V, c->sigma, c->rowI,
+                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->part_row, c->part_col, c->st,
+                    c->info, c->hist};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->Ipin) (void)hipHostFree(c->Ipin);
+    if (c->Jpin) (void)hipHostFree(c->Jpin);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->ev_made)
+        for (int i = 0; i < kRing; ++i)
+            for (int j = 0; j < 5; ++j) (void)hipEventDestroy(c->ev[i][j]);
+    for (int h = 0; h < 2; ++h)
+        if (c->h2d[h]) (void)hipEventDestroy(c->h2d[h]);
+}
+
+double zeta_at(const ircur_params& p, int k) { return p.zeta0 * std::pow(p.gamma, (double)k); }
+
+// Reset device state, factors and history to L_0 = 0, k = 0.
+int reset_state(ircur_ctx* c) {
+    const size_t fa = (size_t)c->R * c->p.n1 * c->fsz, fb = (size_t)c->R * c->p.n2 * c->fsz;
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(c, hipMemsetAsync(c->At[i], 0, fa, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->B[i], 0, fb, c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->hist, 0, sizeof(double) * c->p.max_iter, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->info, 0, sizeof(SvdInfo) * c->p.max_iter, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->k = 0;
+    c->k_enq = 0;
+    c->acc_next = 0;
+    c->stopped = false;
+    c->have_prevV = false;
+    c->lastJ.clear();
+    c->tsum[0] = c->tsum[1] = c->tsum[2] = c->tsum[3] = 0.0;
+    c->tcount = 0;
+    return IRCUR_OK;
+}
+
+// Sum the kernel times of iteration `it` (its events must have completed).
+void accumulate_timing(ircur_ctx* c, int it) {
+    const int slot = it % kRing;
+    for (int q = 0; q < 4; ++q) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[slot][q], c->ev[slot][q + 1]) == hipSuccess) c->tsum[q] += ms;
+    }
+    c->tcount += 1;
+}
+
+int read_state(ircur_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->k = c->st_host->k_done;
+    c->stopped = c->st_host->stop != 0;
+    // every enqueued launch has finished: iterations past k were no-ops
+    c->k_enq = c->k;
+    if (c->timing && c->ev_made) {
+        for (int it = c->acc_next; it < c->k; ++it) accumulate_timing(c, it);
+        c->acc_next = c->k;
+    }
+    return IRCUR_OK;
+}
+
+int status_after(ircur_ctx* c) {
+    if (c->st_host->svd_fail) return fail(c, IRCUR_ERR_SVD, "SVD grid barrier timed out");
+    if (c->st_host->nonfinite) return fail(c, IRCUR_ERR_NONFINITE, "non-finite value in D or iterates");
+    return IRCUR_OK;
+}
+
+// Enqueue iteration k (0-based) with the index sets already on the device.
+int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, const int32_t* Jhost) {
+    const int slot = k % kRing;
+    if (c->timing && c->acc_next <= k - kRing) {
+        // the slot is about to be reused: its iteration has to be summed first
+        for (int it = c->acc_next; it <= k - kRing; ++it) {
+            HIPCHK(c, hipEventSynchronize(c->ev[it % kRing][4]));
+            accumulate_timing(c, it);
+        }
+        c->acc_next = k - kRing + 1;
+    }
+    const ircur_params& p = c->p;
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double zeta = zeta_at(p, k);
+    const float zf = round_down_float(zeta);
+    hipStream_t s = c->stream;
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][0], s));
+
+    CoreArgs ca{};
+    ca.D = c->D; ca.ldD = p.ldD; ca.I = Id; ca.J = Jd; ca.sI = p.sI; ca.sJ = p.sJ;
+    ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
+    ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.st = c->st;
+    HIPCHK(c, launch_core(ca, p.dtype, c->R, s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][1], s));
+
+    SvdArgs sa{};
+    sa.M = c->M; sa.sI = p.sI; sa.sJ = p.sJ; sa.r = p.r; sa.R = c->R; sa.p = c->psvd;
+    sa.G = c->G; sa.bs = c->bs;
+    sa.max_it = p.svd_max_it > 0 ? p.svd_max_it : 64;
+    sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-12 : 1e-9);
+    bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
+                 std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
+    sa.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
+    sa.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
+    sa.prevV = c->prevV; sa.prevV_out = c->prevV;
+    sa.I = Id; sa.J = Jd; sa.n1 = p.n1; sa.n2 = p.n2;
+    sa.At = c->At[cur]; sa.B = c->B[cur];
+    sa.Zp = c->Zp; sa.Gp = c->Gp; sa.Tp = c->Tp;
+    sa.W = c->W; sa.V = c->V; sa.sigma = c->sigma;
+    sa.rowI = c->rowI; sa.rowJ = c->rowJ; sa.GmI = c->GmI; sa.GmJ = c->GmJ; sa.scaleJ = c->scaleJ;
+    sa.info = c->info + k; sa.st = c->st;
+    HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
+    c->have_prevV = true;
+    c->lastJ.assign(Jhost, Jhost + p.sJ);
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
+
+    PassArgs pa{};
+    SideArgs& r0 = pa.side[0];
+    r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
+    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outscale = nullptr; r0.out = c->B[nxt];
+    r0.part = c->part_row; r0.nwg = c->nwg_row;
+    SideArgs& r1 = pa.side[1];
+    r1.X = c->Dt; r1.ldX = c->ldDt; r1.rows = Jd; r1.s = p.sJ; r1.n = p.n1; r1.P = c->At[cur];
+    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outscale = c->scaleJ; r1.out = c->At[nxt];
+    r1.part = c->part_col; r1.nwg = c->nwg_col;
+    pa.zeta = zeta; pa.zeta_f = zf; pa.err_mode = p.err_mode; pa.st = c->st;
+    HIPCHK(c, launch_pass(pa, p.dtype, c->R, s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][3], s));
+
+    FinArgs fa{};
+    fa.part_row = c->part_row; fa.nrow = c->nwg_row; fa.part_col = c->part_col; fa.ncol = c->nwg_col;
+    fa.k = k; fa.max_iter = p.max_iter; fa.eps = p.eps; fa.hist = c->hist; fa.st = c->st;
+    HIPCHK(c, launch_finalize(fa, s));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][4], s));
+    return IRCUR_OK;
+}
+
+void sorted_copy(const int32_t* src, int32_t n, int32_t* dst) {
+    std::copy(src, src + n, dst);
+    std::sort(dst, dst + n);
+}
+
+// Enqueue iterations k0 .. k0+n-1 (k0 = next to enqueue) with sampled sets,
+// or one iteration with the given pair.  Batches alternate between the two
+// halves of the index-set ring; a half is rewritten only after the copy that
+// last read its pinned host buffer has completed.
+int enqueue_chunk(ircur_ctx* c, int n, const int32_t* Igiven, const int32_t* Jgiven) {
+    const ircur_params& p = c->p;
+    const int k0 = c->k_enq;
+    if (n > kChunk) n = kChunk;
+    const int h = c->batch & 1;
+    if (c->h2d_pending[h]) {
+        HIPCHK(c, hipEventSynchronize(c->h2d[h]));
+        c->h2d_pending[h] = false;
+    }
+    const size_t strI = (size_t)p.sI + kIndexPad, strJ = (size_t)p.sJ + kIndexPad;
+    int32_t* Ibase = c->Ipin + (size_t)h * kChunk * strI;
+    int32_t* Jbase = c->Jpin + (size_t)h * kChunk * strJ;
+    int32_t* Idbase = c->Idev + (size_t)h * kChunk * strI;
+    int32_t* Jdbase = c->Jdev + (size_t)h * kChunk * strJ;
+    for (int j = 0; j < n; ++j) {
+        const int k = k0 + j;
+        int32_t* Ih = Ibase + (size_t)j * strI;
+        int32_t* Jh = Jbase + (size_t)j * strJ;
+        if (Igiven) {
+            sorted_copy(Igiven, p.sI, Ih);
+            sorted_copy(Jgiven, p.sJ, Jh);
+        } else {
+            SplitMix64 g = index_stream(p.seed, p.resample ? k : 0);
+            floyd(g, p.n1, p.sI, Ih);
+            floyd(g, p.n2, p.sJ, Jh);
+        }
+        std::fill(Ih + p.sI, Ih + strI, Ih[p.sI - 1]);
+        std::fill(Jh + p.sJ, Jh + strJ, Jh[p.sJ - 1]);
+        if (k < p.max_iter) {
+            std::copy(Ih, Ih + p.sI, c->setsI.begin() + (size_t)k * p.sI);
+            std::copy(Jh, Jh + p.sJ, c->setsJ.begin() + (size_t)k * p.sJ);
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(Idbase, Ibase, sizeof(int32_t) * n * strI, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Jdbase, Jbase, sizeof(int32_t) * n * strJ, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->h2d[h], c->stream));
+    c->h2d_pending[h] = true;
+    c->batch += 1;
+    for (int j = 0; j < n; ++j) {
+        const int rc = enqueue_iter(c, k0 + j, Idbase + (size_t)j * strI, Jdbase + (size_t)j * strJ,
+                                    Jbase + (size_t)j * strJ);
+        if (rc) return rc;
+        c->k_enq = k0 + j + 1;
+    }
+    return IRCUR_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ===
+
+extern "C" {
+
+int ircur_params_default(ircur_params* p) {
+    if (!p) return IRCUR_ERR_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->gamma = 0.7;
+    p->eps = 1e-5;
+    p->max_iter = 100;
+    p->resample = 1;
+    p->err_mode = 0;
+    p->dtype = IRCUR_F64;
+    return IRCUR_OK;
+}
+
+int ircur_sample(uint64_t seed, int64_t t, int64_t n1, int64_t n2, int32_t sI, int32_t sJ,
+                 int32_t* I_host, int32_t* J_host) {
+    if (!I_host || !J_host || n1 < 1 || n2 < 1 || sI < 0 || sJ < 0 || sI > n1 || sJ > n2 || t < 0)
+        return IRCUR_ERR_ARG;
+    SplitMix64 g = index_stream(seed, t);
+    floyd(g, n1, sI, I_host);
+    floyd(g, n2, sJ, J_host);
+    return IRCUR_OK;
+}
+
+int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, const void* Dt_dev,
+               int64_t ldDt, void* stream) {
+    if (!out) return IRCUR_ERR_ARG;
+    *out = nullptr;
+    int rc = validate(pin, D_dev, Dt_dev, ldDt);
+    if (rc) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRCUR_ERR_DEVICE;
+
+    ircur_ctx* c = new (std::nothrow) ircur_ctx();
+    if (!c) return IRCUR_ERR_ALLOC;
+    c->p = *pin;
+    const ircur_params& p = c->p;
+    c->R = pad_rank(p.r);
+    const int smin = std::min(p.sI, p.sJ);
+    int pb = p.svd_block ? p.svd_block : std::min(std::min(smin, 32), p.r + std::max(4, p.r / 2));
+    c->G = std::max(1, std::min(8, (p.sI + 15) / 16));
+    c->bs = (p.sI + c->G - 1) / c->G;
+    size_t lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
+    while (lds > 160 * 1024 && pb > p.r) {
+        --pb;
+        lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
+    }
+    if (lds > 160 * 1024) { delete c; return IRCUR_ERR_UNSUPPORTED; }
+    c->psvd = pb;
+    c->svd_lds = lds;
+    c->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
+    c->esz = p.dtype == IRCUR_F64 ? 8 : (p.dtype == IRCUR_F32 ? 4 : 2);
+    c->fsz = p.dtype == IRCUR_F64 ? 8 : 4;
+    c->D = D_dev;
+    c->nwg_row = (int)((p.n2 + 63) / 64);
+    c->nwg_col = (int)((p.n1 + 63) / 64);
+
+#define TRY(x)                      \
+    do {                            \
+        int r_ = (x);               \
+        if (r_) {                   \
+            free_all(c);            \
+            delete c;               \
+            return r_;              \
+        }                           \
+    } while (0)
+    const size_t R = c->R;
+    for (int i = 0; i < 2; ++i) {
+        TRY(dalloc_bytes(c, &c->At[i], R * p.n1 * c->fsz));
+        TRY(dalloc_bytes(c, &c->B[i], R * p.n2 * c->fsz));
+    }
+    TRY(dalloc(c, &c->Idev, (size_t)kRing * (p.sI + kIndexPad)));
+    TRY(dalloc(c, &c->Jdev, (size_t)kRing * (p.sJ + kIndexPad)));
+    if (hipEventCreateWithFlags(&c->h2d[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->h2d[1], hipEventDisableTiming) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return IRCUR_ERR_DEVICE;
+    }
+    if (hipHostMalloc((void**)&c->Ipin, sizeof(int32_t) * kRing * (p.sI + kIndexPad), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->Jpin, sizeof(int32_t) * kRing * (p.sJ + kIndexPad), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return IRCUR_ERR_ALLOC;
+    }
+    TRY(dalloc(c, &c->M, (size_t)p.sI * p.sJ));
+    TRY(dalloc(c, &c->Zp, (size_t)c->G * p.sJ * c->psvd));
+    TRY(dalloc(c, &c->Gp, (size_t)c->G * c->psvd * c->psvd));
+    TRY(dalloc(c, &c->Tp, (size_t)c->G * R * R));
+    TRY(dalloc(c, &c->prevV, (size_t)p.sJ * c->psvd));
+    TRY(dalloc(c, &c->W, (size_t)p.sI * R));
+    TRY(dalloc(c, &c->V, (size_t)p.sJ * R));
+    TRY(dalloc(c, &c->sigma, R));
+    TRY(dalloc_bytes(c, &c->rowI, (size_t)p.sI * 3 * R * c->fsz));
+    TRY(dalloc_bytes(c, &c->rowJ, (size_t)p.sJ * 3 * R * c->fsz));
+    TRY(dalloc_bytes(c, &c->GmI, R * R * c->fsz));
+    TRY(dalloc_bytes(c, &c->GmJ, R * R * c->fsz));
+    TRY(dalloc_bytes(c, &c->scaleJ, R * c->fsz));
+    TRY(dalloc(c, &c->part_row, (size_t)2 * c->nwg_row));
+    TRY(dalloc(c, &c->part_col, (size_t)2 * c->nwg_col));
+    TRY(dalloc(c, &c->st, 1));
+    TRY(dalloc(c, &c->info, (size_t)p.max_iter));
+    TRY(dalloc(c, &c->hist, (size_t)p.max_iter));
+    c->setsI.assign((size_t)p.max_iter * p.sI, 0);
+    c->setsJ.assign((size_t)p.max_iter * p.sJ, 0);
+    if (Dt_dev) {
+        c->Dt = Dt_dev;
+        c->ldDt = ldDt;
+    } else {
+        TRY(dalloc_bytes(c, &c->Dt_own, (size_t)p.n1 * p.n2 * c->esz));
+        c->Dt = c->Dt_own;
+        c->ldDt = p.n1;
+        hipError_t e = launch_transpose(D_dev, p.ldD, c->Dt_own, p.n1, p.n1, p.n2, (int)c->esz, c->stream);
+        if (e != hipSuccess) { free_all(c); delete c; return IRCUR_ERR_DEVICE; }
+    }
+    TRY(reset_state(c));
+#undef TRY
+    *out = c;
+    return IRCUR_OK;
+}
+
+int ircur_reset(ircur_ctx* c) {
+    if (!c) return IRCUR_ERR_ARG;
+    return reset_state(c);
+}
+
+int ircur_step(ircur_ctx* c, const int32_t* I_host, const int32_t* J_host, double* e_out) {
+    if (!c) return IRCUR_ERR_ARG;
+    if ((I_host == nullptr) != (J_host == nullptr)) return fail(c, IRCUR_ERR_ARG, "give both I and J or neither");
+    const ircur_params& p = c->p;
+    if (I_host) {
+        std::vector<int32_t> a(I_host, I_host + p.sI), b(J_host, J_host + p.sJ);
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        for (int i = 0; i < p.sI; ++i)
+            if (a[i] < 0 || a[i] >= p.n1 || (i && a[i] == a[i - 1])) return fail(c, IRCUR_ERR_ARG, "I must hold distinct indices in [0, n1)");
+        for (int i = 0; i < p.sJ; ++i)
+            if (b[i] < 0 || b[i] >= p.n2 || (i && b[i] == b[i - 1])) return fail(c, IRCUR_ERR_ARG, "J must hold distinct indices in [0, n2)");
+    }
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (c->stopped || c->k >= p.max_iter) return fail(c, IRCUR_ERR_STATE, "run already stopped");
+    rc = enqueue_chunk(c, 1, I_host, J_host);
+    if (rc) return rc;
+    rc = read_state(c);
+    if (rc) return rc;
+    if (e_out) *e_out = c->st_host->e_last;
+    return status_after(c);
+}
+
+int ircur_enqueue(ircur_ctx* c, int32_t n_iter) {
+    if (!c || n_iter < 0) return IRCUR_ERR_ARG;
+    while (n_iter > 0) {
+        if (c->stopped || c->k_enq >= c->p.max_iter) break;
+        const int n = std::min<int>(std::min(n_iter, kChunk), c->p.max_iter - c->k_enq);
+        int rc = enqueue_chunk(c, n, nullptr, nullptr);
+        if (rc) return rc;
+        n_iter -= n;
+    }
+    return IRCUR_OK;
+}
+
+int ircur_sync(ircur_ctx* c, int32_t* k_out, double* e_out) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (k_out) *k_out = c->k;
+    if (e_out) *e_out = c->st_host->e_last;
+    return status_after(c);
+}
+
+int ircur_solve(ircur_ctx* c, int32_t* iters_out, double* e_out) {
+    if (!c) return IRCUR_ERR_ARG;
+    const ircur_params& p = c->p;
+    int rc0 = read_state(c);
+    if (rc0) return rc0;
+    int chunk = 2;
+    while (!c->stopped && c->k < p.max_iter) {
+        const int n = std::min(chunk, p.max_iter - c->k_enq);
+        int rc = enqueue_chunk(c, n, nullptr, nullptr);
+        if (rc) return rc;
+        rc = read_state(c);
+        if (rc) return rc;
+        rc = status_after(c);
+        if (rc) return rc;
+        chunk = std::min(chunk * 2, kChunk);
+    }
+    if (iters_out) *iters_out = c->k;
+    const double e = c->k > 0 ? c->st_host->e_last : 1.0;
+    if (e_out) *e_out = e;
+    return (e <= p.eps) ? IRCUR_OK : IRCUR_NOT_CONVERGED;
+}
+
+int ircur_get_factors(ircur_ctx* c, void* At_dev, void* B_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const int cur = c->k & 1;
+    const size_t r = c->p.r;
+    if (At_dev) HIPCHK(c, hipMemcpyAsync(At_dev, c->At[cur], r * c->p.n1 * c->fsz, hipMemcpyDeviceToDevice, c->stream));
+    if (B_dev) HIPCHK(c, hipMemcpyAsync(B_dev, c->B[cur], r * c->p.n2 * c->fsz, hipMemcpyDeviceToDevice, c->stream));
+    return IRCUR_OK;
+}
+
+int ircur_set_factors(ircur_ctx* c, const void* At_dev, const void* B_dev, int32_t k) {
+    if (!c || !At_dev || !B_dev || k < 0 || k >= c->p.max_iter) return IRCUR_ERR_ARG;
+    const int cur = k & 1;
+    const size_t r = c->p.r, R = c->R;
+    HIPCHK(c, hipMemsetAsync(c->At[cur], 0, R * c->p.n1 * c->fsz, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->B[cur], 0, R * c->p.n2 * c->fsz, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->At[cur], At_dev, r * c->p.n1 * c->fsz, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->B[cur], B_dev, r * c->p.n2 * c->fsz, hipMemcpyDeviceToDevice, c->stream));
+    DevState h{};
+    h.k_done = k;
+    *c->st_host = h;
+    HIPCHK(c, hipMemcpyAsync(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->k = k;
+    c->k_enq = k;
+    c->acc_next = k;
+    c->stopped = false;
+    c->have_prevV = false;
+    return IRCUR_OK;
+}
+
+int ircur_get_history(ircur_ctx* c, double* e_host, int32_t cap, int32_t* n_out) {
+    if (!c || (!e_host && cap > 0) || cap < 0) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const int n = std::min(cap, c->k);
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(e_host, c->hist, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (n_out) *n_out = n;
+    return IRCUR_OK;
+}
+
+int ircur_get_sets(ircur_ctx* c, int32_t* I_host, int32_t* J_host) {
+    if (!c || !I_host || !J_host) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (c->k < 1) return fail(c, IRCUR_ERR_STATE, "no completed iteration");
+    const size_t k = c->k - 1;
+    std::copy(c->setsI.begin() + k * c->p.sI, c->setsI.begin() + (k + 1) * c->p.sI, I_host);
+    std::copy(c->setsJ.begin() + k * c->p.sJ, c->setsJ.begin() + (k + 1) * c->p.sJ, J_host);
+    return IRCUR_OK;
+}
+
+int ircur_get_core(ircur_ctx* c, double* M_dev, double* W_dev, double* sigma_dev, double* V_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    const ircur_params& p = c->p;
+    const size_t R = c->R, r = p.r;
+    if (M_dev) HIPCHK(c, hipMemcpyAsync(M_dev, c->M, sizeof(double) * p.sI * p.sJ, hipMemcpyDeviceToDevice, c->stream));
+    if (W_dev) HIPCHK(c, hipMemcpy2DAsync(W_dev, r * sizeof(double), c->W, R * sizeof(double), r * sizeof(double), p.sI, hipMemcpyDeviceToDevice, c->stream));
+    if (V_dev) HIPCHK(c, hipMemcpy2DAsync(V_dev, r * sizeof(double), c->V, R * sizeof(double), r * sizeof(double), p.sJ, hipMemcpyDeviceToDevice, c->stream));
+    if (sigma_dev) HIPCHK(c, hipMemcpyAsync(sigma_dev, c->sigma, sizeof(double) * r, hipMemcpyDeviceToDevice, c->stream));
+    return IRCUR_OK;
+}
+
+int ircur_get_info(ircur_ctx* c, int32_t* svd_iters, double* svd_resid, double* gap, int32_t* kept) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (c->k < 1) return fail(c, IRCUR_ERR_STATE, "no completed iteration");
+    SvdInfo h{};
+    HIPCHK(c, hipMemcpy(&h, c->info + (c->k - 1), sizeof(SvdInfo), hipMemcpyDeviceToHost));
+    if (svd_iters) *svd_iters = h.iters;
+    if (svd_resid) *svd_resid = h.resid;
+    if (gap) *gap = h.gap;
+    if (kept) *kept = h.kept;
+    return IRCUR_OK;
+}
+
+int ircur_set_timing(ircur_ctx* c, int32_t enable) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    c->acc_next = c->k;
+    if (enable && !c->ev_made) {
+        for (int i = 0; i < kRing; ++i)
+            for (int j = 0; j < 5; ++j) HIPCHK(c, hipEventCreate(&c->ev[i][j]));
+        c->ev_made = true;
+    }
+    c->timing = enable != 0;
+    c->tsum[0] = c->tsum[1] = c->tsum[2] = c->tsum[3] = 0.0;
+    c->tcount = 0;
+    return IRCUR_OK;
+}
+
+int ircur_get_timing(ircur_ctx* c, double* ms4, int64_t* count) {
+    if (!c || !ms4) return IRCUR_ERR_ARG;
+    for (int q = 0; q < 4; ++q) ms4[q] = c->tsum[q];
+    if (count) *count = c->tcount;
+    return IRCUR_OK;
+}
+
+int ircur_get_state(ircur_ctx* c, void* buf, size_t* bytes) {
+    if (!c || !bytes) return IRCUR_ERR_ARG;
+    const ircur_params& p = c->p;
+    const size_t fa = (size_t)c->R * p.n1 * c->fsz, fb = (size_t)c->R * p.n2 * c->fsz;
+    const size_t need = 64 + fa + fb + sizeof(double) * p.max_iter;
+    if (!buf) { *bytes = need; return IRCUR_OK; }
+    if (*bytes < need) return fail(c, IRCUR_ERR_ARG, "state buffer too small");
+    int rc = read_state(c);
+    if (rc) return rc;
+    char* o = (char*)buf;
+    std::memset(o, 0, 64);
+    const int64_t hdr[6] = {0x49524355520001LL, c->k, c->stopped ? 1 : 0, p.n1, p.n2, c->R};
+    std::memcpy(o, hdr, sizeof(hdr));
+    const int cur = c->k & 1;
+    HIPCHK(c, hipMemcpy(o + 64, c->At[cur], fa, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(o + 64 + fa, c->B[cur], fb, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(o + 64 + fa + fb, c->hist, sizeof(double) * p.max_iter, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return IRCUR_OK;
+}
+
+int ircur_set_state(ircur_ctx* c, const void* buf, size_t bytes) {
+    if (!c || !buf) return IRCUR_ERR_ARG;
+    const ircur_params& p = c->p;
+    const size_t fa = (size_t)c->R * p.n1 * c->fsz, fb = (size_t)c->R * p.n2 * c->fsz;
+    const size_t need = 64 + fa + fb + sizeof(double) * p.max_iter;
+    if (bytes < need) return fail(c, IRCUR_ERR_ARG, "state buffer too small");
+    int64_t hdr[6];
+    std::memcpy(hdr, buf, sizeof(hdr));
+    if (hdr[0] != 0x49524355520001LL || hdr[3] != p.n1 || hdr[4] != p.n2 || hdr[5] != c->R ||
+        hdr[1] < 0 || hdr[1] > p.max_iter)
+        return fail(c, IRCUR_ERR_ARG, "state does not match this context");
+    const int k = (int)hdr[1];
+    const char* o = (const char*)buf;
+    const int cur = k & 1;
+    HIPCHK(c, hipMemcpy(c->At[cur], o + 64, fa, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->B[cur], o + 64 + fa, fb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->hist, o + 64 + fa + fb, sizeof(double) * p.max_iter, hipMemcpyHostToDevice));
+    double e_last = 1.0;
+    if (k > 0) std::memcpy(&e_last, o + 64 + fa + fb + sizeof(double) * (k - 1), sizeof(double));
+    DevState h{};
+    h.k_done = k;
+    h.stop = (int32_t)hdr[2];
+    h.e_last = e_last;
+    HIPCHK(c, hipMemcpy(c->st, &h, sizeof(DevState), hipMemcpyHostToDevice));
+    c->k = k;
+    c->k_enq = k;
+    c->acc_next = k;
+    c->stopped = hdr[2] != 0;
+    c->have_prevV = false;
+    return IRCUR_OK;
+}
+
+void ircur_destroy(ircur_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char* ircur_strerror(int s) {
+    switch (s) {
+        case IRCUR_OK: return "ok";
+        case IRCUR_NOT_CONVERGED: return "iteration cap reached before e <= eps";
+        case IRCUR_WARN_RANK_DEFICIENT: return "components of U^+ dropped (rank-deficient core)";
+        case IRCUR_WARN_SVD_INEXACT: return "top-r SVD reached its iteration cap";
+        case IRCUR_ERR_ARG: return "invalid argument";
+        case IRCUR_ERR_ALLOC: return "device allocation failed";
+        case IRCUR_ERR_DEVICE: return "HIP error or no device";
+        case IRCUR_ERR_SVD: return "SVD failure";
+        case IRCUR_ERR_NONFINITE: return "non-finite value";
+        case IRCUR_ERR_STATE: return "invalid state for this call";
+        case IRCUR_ERR_UNSUPPORTED: return "sizes beyond a kernel limit";
+        default: return "unknown status";
+    }
+}
+
+const char* ircur_last_error(const ircur_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

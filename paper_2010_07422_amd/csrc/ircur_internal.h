@@ -1,0 +1,132 @@
+// Internal declarations shared by the IRCUR HIP kernels and the host runtime.
+// Not part of the public ABI (see include/ircur.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ircur {
+
+// Padded ranks the factor kernels are compiled for; a rank r runs as the
+// smallest entry >= r with the extra factor rows held at zero.
+constexpr int kRanks[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
+// Trailing entries after every stored index set (copies of its last index):
+// the pass kernel reads up to this many indices past the rows it uses.
+constexpr int kIndexPad = 16;
+
+inline int pad_rank(int r) {
+    for (int v : kRanks) if (v >= r) return v;
+    return -1;
+}
+
+// Device-resident run state (one per context).  Written only by kernels,
+// read by the host after a synchronisation.
+struct DevState {
+    int32_t stop;        // 1 once e <= eps, k = max_iter or an error occurred
+    int32_t k_done;      // completed iterations
+    int32_t nonfinite;   // a NaN/Inf was met
+    int32_t svd_fail;    // the SVD's grid barrier timed out
+    int32_t svd_capped;  // an SVD hit its iteration cap
+    int32_t rank_drop;   // a component of U^+ was dropped by the pinv rule
+    double e_last;
+    uint32_t bar_ctr;    // grid-barrier counter of the SVD kernel
+    uint32_t pad_;
+};
+
+// Per-iteration SVD diagnostics, one record per iteration.
+struct SvdInfo {
+    int32_t iters;
+    int32_t kept;
+    double resid;        // max_i ||M^T w_i - sigma_i v_i|| / sigma_1
+    double gap;          // sigma_{r+1} / sigma_r (Ritz estimate, 0 if p == r)
+};
+
+// Arguments of the fused row/column pass.  "Side" 0 is the row pass over
+// D[I, :] (output B_{k+1}); side 1 is the column pass over D^T[J, :] (output
+// A_{k+1}^T).  Both have the same shape: s gathered rows of length n.
+struct SideArgs {
+    const void* X;         // D (side 0) or D^T (side 1)
+    int64_t ldX;
+    const int32_t* rows;   // I or J, s entries
+    int32_t s;
+    int64_t n;             // row length (n2 or n1)
+    const void* P;         // B_k (side 0) or A_k^T (side 1): R x n, row stride n
+    const void* rowdata;   // s x 3R: [gathered factor | projection | prediction]
+    const void* Gm;        // R x R correction matrix for the residual
+    const void* outscale;  // R scales of the output (nullptr: 1)
+    void* out;             // new factor, R x n, row stride n
+    double* part;          // 2 doubles per workgroup: (residual, ||D_side||^2)
+    int32_t nwg;
+};
+
+struct PassArgs {
+    SideArgs side[2];
+    double zeta;           // threshold zeta_{k+1}
+    float zeta_f;          // largest float <= zeta (exact float comparison)
+    int32_t err_mode;
+    const DevState* st;
+};
+
+struct CoreArgs {
+    const void* D; int64_t ldD;
+    const int32_t* I; const int32_t* J;
+    int32_t sI, sJ;
+    int64_t n1, n2;
+    const void* At;        // A_k^T, R x n1
+    const void* B;         // B_k, R x n2
+    double zeta; float zeta_f;
+    double* M;             // sI x sJ, double
+    DevState* st;
+};
+
+struct SvdArgs {
+    const double* M;       // sI x sJ
+    int32_t sI, sJ, r, R, p;
+    int32_t G;             // workgroups
+    int32_t bs;            // rows of M per workgroup
+    int32_t max_it;
+    double tol;
+    int32_t warm;          // 0 random, 1 previous Ritz vectors, 2 B_k[:, J]^T
+    uint64_t salt;         // random fill salt
+    const double* prevV;   // sJ x p (warm == 1)
+    double* prevV_out;     // sJ x p
+    const int32_t* I; const int32_t* J;
+    int64_t n1, n2;
+    const void* At;        // A_k^T (R x n1), factor dtype
+    const void* B;         // B_k (R x n2), factor dtype
+    double* Zp;            // G x sJ x p scratch
+    double* Gp;            // G x p x p scratch
+    double* Tp;            // G x R x R scratch (Gamma partials)
+    double* W;             // sI x R out
+    double* V;             // sJ x R out
+    double* sigma;         // R out
+    void* rowI;            // sI x 3R (factor dtype)
+    void* rowJ;            // sJ x 3R
+    void* GmI;             // R x R
+    void* GmJ;             // R x R
+    void* scaleJ;          // R
+    SvdInfo* info;         // one record (this iteration)
+    DevState* st;
+};
+
+struct FinArgs {
+    const double* part_row; int32_t nrow;
+    const double* part_col; int32_t ncol;
+    int32_t k;             // iteration index (0-based) being finished
+    int32_t max_iter;
+    double eps;
+    double* hist;          // e history
+    DevState* st;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_transpose(const void* src, int64_t lds, void* dst, int64_t ldd,
+                            int64_t rows, int64_t cols, int elem_bytes, hipStream_t s);
+hipError_t launch_core(const CoreArgs& a, int dtype, int R, hipStream_t s);
+hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s);
+hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+hipError_t launch_set_bar(DevState* st, hipStream_t s);
+size_t svd_lds_bytes(int sJ, int p, int bs, int R);
+
+}  // namespace ircur

@@ -1,0 +1,293 @@
+"""ctypes binding of libircur (the C ABI declared in include/ircur.h).
+
+Argument marshalling only: every step of IRCUR runs in the library's HIP
+kernels.  torch tensors supply device memory and the stream.  The library is
+loaded on first use; a missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libircur.so")
+
+OK, NOT_CONVERGED, WARN_RANK_DEFICIENT, WARN_SVD_INEXACT = 0, 1, 2, 3
+ERR_ARG, ERR_ALLOC, ERR_DEVICE, ERR_SVD, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+F64, F32, BF16 = 0, 1, 2
+MAX_RANK = 32
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("ldD", ctypes.c_int64),
+        ("r", ctypes.c_int32), ("sI", ctypes.c_int32), ("sJ", ctypes.c_int32),
+        ("dtype", ctypes.c_int32), ("resample", ctypes.c_int32), ("err_mode", ctypes.c_int32),
+        ("zeta0", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("svd_tol", ctypes.c_double), ("svd_max_it", ctypes.c_int32), ("svd_block", ctypes.c_int32),
+    ]
+
+
+class IrcurError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "ircur_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "ircur_init": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Params), _P, _P, ctypes.c_int64, _P]),
+    "ircur_step": (ctypes.c_int, [_P, _I32P, _I32P, _DP]),
+    "ircur_enqueue": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ircur_sync": (ctypes.c_int, [_P, _I32P, _DP]),
+    "ircur_solve": (ctypes.c_int, [_P, _I32P, _DP]),
+    "ircur_reset": (ctypes.c_int, [_P]),
+    "ircur_get_factors": (ctypes.c_int, [_P, _P, _P]),
+    "ircur_set_factors": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "ircur_get_history": (ctypes.c_int, [_P, _DP, ctypes.c_int32, _I32P]),
+    "ircur_get_sets": (ctypes.c_int, [_P, _I32P, _I32P]),
+    "ircur_get_core": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "ircur_get_cur": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "ircur_to_svd": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ircur_sparse_full": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "ircur_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "ircur_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "ircur_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ircur_get_timing": (ctypes.c_int, [_P, _DP, ctypes.POINTER(ctypes.c_int64)]),
+    "ircur_get_info": (ctypes.c_int, [_P, _I32P, _DP, _DP, _I32P]),
+    "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
+    "ircur_destroy": (None, [_P]),
+    "ircur_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ircur_last_error": (ctypes.c_char_p, [_P]),
+}
+
+
+def lib():
+    """Load libircur.so (raises FileNotFoundError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with "
+                                    "`python -m paper_2010_07422_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().ircur_strerror(code).decode()
+
+
+def sample(seed: int, t: int, n1: int, n2: int, sI: int, sJ: int):
+    """The library's index sampler (host): sorted I (sI of n1), J (sJ of n2)."""
+    I = np.zeros(sI, np.int32)
+    J = np.zeros(sJ, np.int32)
+    rc = lib().ircur_sample(seed, t, n1, n2, sI, sJ, I.ctypes.data_as(_I32P), J.ctypes.data_as(_I32P))
+    if rc != OK:
+        raise IrcurError(rc, strerror(rc))
+    return I, J
+
+
+def _dtype_code(t):
+    import torch
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t]
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(_I32P)
+
+
+@dataclass
+class Info:
+    svd_iters: int
+    svd_resid: float
+    gap: float
+    kept: int
+
+
+class IRCUR:
+    """One IRCUR context over a device matrix D (torch tensor, float64 /
+    float32 / bfloat16, row-major with unit column stride)."""
+
+    def __init__(self, D, r, sI, sJ, zeta0, gamma=0.7, eps=1e-5, max_iter=100, seed=0,
+                 resample=True, err_mode=0, Dt=None, svd_tol=0.0, svd_max_it=0,
+                 svd_block=0, stream=None):
+        import torch
+        if not (isinstance(D, torch.Tensor) and D.is_cuda and D.dim() == 2 and D.stride(1) == 1):
+            raise ValueError("D must be a 2-D CUDA tensor with unit column stride")
+        self.D = D
+        self.Dt = Dt
+        self.dtype = _dtype_code(D.dtype)
+        self.fdtype = torch.float64 if self.dtype == F64 else torch.float32
+        p = Params()
+        lib().ircur_params_default(ctypes.byref(p))
+        p.n1, p.n2 = D.shape
+        p.ldD = D.stride(0)
+        p.r, p.sI, p.sJ = r, sI, sJ
+        p.dtype = self.dtype
+        p.resample = 1 if resample else 0
+        p.err_mode = err_mode
+        p.zeta0, p.gamma, p.eps = float(zeta0), float(gamma), float(eps)
+        p.max_iter = max_iter
+        p.seed = seed
+        p.svd_tol, p.svd_max_it, p.svd_block = float(svd_tol), svd_max_it, svd_block
+        self.p = p
+        self.stream = stream
+        h = ctypes.c_void_p()
+        ldDt = 0 if Dt is None else Dt.stride(0)
+        rc = lib().ircur_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(D.data_ptr()),
+                              None if Dt is None else ctypes.c_void_p(Dt.data_ptr()),
+                              ldDt, _stream_handle(stream))
+        if rc != OK:
+            raise IrcurError(rc, "ircur_init: " + strerror(rc))
+        self.h = h
+
+    # ------------------------------------------------------------ control
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = lib().ircur_last_error(self.h).decode()
+            raise IrcurError(rc, f"{what}: {strerror(rc)}: {msg}")
+        return rc
+
+    def step(self, I=None, J=None):
+        e = ctypes.c_double()
+        if I is None:
+            rc = lib().ircur_step(self.h, None, None, ctypes.byref(e))
+        else:
+            Ia, Ip = _i32(I)
+            Ja, Jp = _i32(J)
+            rc = lib().ircur_step(self.h, Ip, Jp, ctypes.byref(e))
+        self._check(rc, "ircur_step")
+        return e.value
+
+    def solve(self):
+        it = ctypes.c_int32()
+        e = ctypes.c_double()
+        rc = self._check(lib().ircur_solve(self.h, ctypes.byref(it), ctypes.byref(e)), "ircur_solve")
+        return it.value, e.value, rc
+
+    def enqueue(self, n):
+        self._check(lib().ircur_enqueue(self.h, n), "ircur_enqueue")
+
+    def sync(self):
+        k = ctypes.c_int32()
+        e = ctypes.c_double()
+        self._check(lib().ircur_sync(self.h, ctypes.byref(k), ctypes.byref(e)), "ircur_sync")
+        return k.value, e.value
+
+    def reset(self):
+        self._check(lib().ircur_reset(self.h), "ircur_reset")
+
+    # ------------------------------------------------------------ outputs
+    def factors(self):
+        """(A^T, B): r x n1 and r x n2 tensors, L_k = A B."""
+        import torch
+        n1, n2, r = self.p.n1, self.p.n2, self.p.r
+        At = torch.empty((r, n1), dtype=self.fdtype, device=self.D.device)
+        B = torch.empty((r, n2), dtype=self.fdtype, device=self.D.device)
+        self._check(lib().ircur_get_factors(self.h, ctypes.c_void_p(At.data_ptr()),
+                                            ctypes.c_void_p(B.data_ptr())), "ircur_get_factors")
+        self._sync_stream()
+        return At, B
+
+    def set_factors(self, At, B, k):
+        At = At.to(self.fdtype).contiguous()
+        B = B.to(self.fdtype).contiguous()
+        self._check(lib().ircur_set_factors(self.h, ctypes.c_void_p(At.data_ptr()),
+                                            ctypes.c_void_p(B.data_ptr()), k), "ircur_set_factors")
+
+    def history(self):
+        cap = self.p.max_iter
+        buf = np.zeros(cap, np.float64)
+        n = ctypes.c_int32()
+        self._check(lib().ircur_get_history(self.h, buf.ctypes.data_as(_DP), cap, ctypes.byref(n)),
+                    "ircur_get_history")
+        return buf[: n.value].tolist()
+
+    def sets(self):
+        I = np.zeros(self.p.sI, np.int32)
+        J = np.zeros(self.p.sJ, np.int32)
+        self._check(lib().ircur_get_sets(self.h, I.ctypes.data_as(_I32P), J.ctypes.data_as(_I32P)),
+                    "ircur_get_sets")
+        return I, J
+
+    def core(self):
+        """(M, W_r, sigma_r, V_r) of the last iteration, float64 tensors."""
+        import torch
+        sI, sJ, r = self.p.sI, self.p.sJ, self.p.r
+        dev = self.D.device
+        M = torch.empty((sI, sJ), dtype=torch.float64, device=dev)
+        W = torch.empty((sI, r), dtype=torch.float64, device=dev)
+        s = torch.empty((r,), dtype=torch.float64, device=dev)
+        V = torch.empty((sJ, r), dtype=torch.float64, device=dev)
+        self._check(lib().ircur_get_core(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in (M, W, s, V))),
+                    "ircur_get_core")
+        self._sync_stream()
+        return M, W, s, V
+
+    def info(self):
+        it = ctypes.c_int32()
+        res = ctypes.c_double()
+        gap = ctypes.c_double()
+        kept = ctypes.c_int32()
+        self._check(lib().ircur_get_info(self.h, ctypes.byref(it), ctypes.byref(res), ctypes.byref(gap),
+                                         ctypes.byref(kept)), "ircur_get_info")
+        return Info(it.value, res.value, gap.value, kept.value)
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        self._check(lib().ircur_get_state(self.h, None, ctypes.byref(n)), "ircur_get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().ircur_get_state(self.h, buf, ctypes.byref(n)), "ircur_get_state")
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(lib().ircur_set_state(self.h, buf, len(blob)), "ircur_set_state")
+
+    def set_timing(self, on: bool):
+        self._check(lib().ircur_set_timing(self.h, 1 if on else 0), "ircur_set_timing")
+
+    def timing(self):
+        ms = (ctypes.c_double * 4)()
+        cnt = ctypes.c_int64()
+        self._check(lib().ircur_get_timing(self.h, ms, ctypes.byref(cnt)), "ircur_get_timing")
+        return list(ms), cnt.value
+
+    def _sync_stream(self):
+        import torch
+        (torch.cuda.current_stream() if self.stream is None else self.stream).synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ircur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,74 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative, Frobenius): 1e-10 for FP64 runs, 1e-5 for FP32, 1e-2
+for BF16 storage.  Mask decisions are compared exactly except where the
+oracle's |x| is within a rounding-sized band of zeta.
+"""
+import numpy as np
+import pytest
+
+from oracle import ircur as O
+from oracle import sampler
+from paper_2010_07422_amd import synth
+from tests.gpu_util import require_gpu, to_dev, factors_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(torch, D, dtype, r, sI, sJ, zeta0, **kw):
+    from paper_2010_07422_amd.ircur import IRCUR
+    Dd = to_dev(torch, D, dtype)
+    return IRCUR(Dd, r, sI, sJ, zeta0, **kw), Dd
+
+
+@pytest.mark.parametrize("n1,n2,r,s1,s2,k", [(700, 650, 4, 60, 55, 3), (257, 300, 1, 20, 31, 0),
+                                              (1000, 1000, 5, 139, 139, 5)])
+def test_single_step_f64(n1, n2, r, s1, s2, k):
+    torch = require_gpu()
+    p = synth.planted(n1, n2, r, 0.1, seed=41 + k)
+    I, J = sampler.draw_IJ(5, 0, n1, n2, s1, s2)
+    A = np.zeros((n1, r)); B = np.zeros((r, n2))
+    z0 = p.Lmax
+    for kk in range(k):
+        out = O.step(p.D, A, B, I, J, z0 * 0.7 ** kk, r)
+        A, B = out["A1"], out["B1"]
+    ref = O.step(p.D, A, B, I, J, z0 * 0.7 ** k, r)
+    print(f"case n1={n1} n2={n2} r={r} s=({s1},{s2}) k={k}", flush=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float64, r, s1, s2, z0, eps=0.0, max_iter=k + 1, seed=5,
+                   resample=False)
+    if k > 0:
+        ctx.set_factors(to_dev(torch, A.T, torch.float64), to_dev(torch, B, torch.float64), k)
+    e = ctx.step(I, J)
+    M, W, s, V = ctx.core()
+    M = M.cpu().numpy(); s = s.cpu().numpy()
+    # core: same entries, same masks away from the threshold
+    assert np.max(np.abs(M - ref["M"])) <= 1e-12 * max(np.abs(ref["M"]).max(), 1e-300)
+    assert np.allclose(s, ref["sigma"], rtol=1e-11, atol=1e-12 * ref["sigma"][0])
+    A1, B1 = factors_np(ctx)
+    assert O.factored_rel_diff(A1, B1, ref["A1"], ref["B1"]) <= 1e-11
+    assert abs(e - ref["e"]) <= 1e-9 * max(ref["e"], 1e-300)
+    ctx.close()
+
+
+def test_run_planted_n1000_r5_f64_matches_oracle():
+    """n = 1000, r = 5, alpha = 0.1, |I| = |J| = 139, IRCUR-R, 30 iterations."""
+    torch = require_gpu()
+    cfg = synth.CONFIGS["planted_n1000_r5_f64"]
+    n, r = cfg["n"], cfg["r"]
+    p = synth.planted(n, n, r, cfg["alpha"], seed=cfg["data_seed"])
+    s = synth.sample_size(cfg["c"], r, n)
+    ref = O.ircur(p.D, r, s, s, p.Lmax, cfg["gamma"], 0.0, cfg["max_iter"], seed=cfg["index_seed"],
+                  resample=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float64, r, s, s, p.Lmax, gamma=cfg["gamma"], eps=0.0,
+                   max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
+    it, e, rc = ctx.solve()
+    assert it == cfg["max_iter"]
+    I, J = ctx.sets()
+    assert np.array_equal(I, ref.I) and np.array_equal(J, ref.J)
+    A, B = factors_np(ctx)
+    d = O.factored_rel_diff(A, B, ref.A, ref.B)
+    print("rel diff vs oracle", d, "e", e, ref.e_hist[-1], flush=True)
+    assert d <= 1e-10
+    h = np.array(ctx.history())
+    assert np.allclose(h, ref.e_hist, rtol=1e-5, atol=0)
+    ctx.close()
