@@ -77,7 +77,7 @@ typedef struct {
                             of D - L_k on the new I, J                            */
     double  zeta0;       /* initial threshold zeta_0 > 0 (0 allowed: removes all)  */
     double  gamma;       /* decay, zeta_{k+1} = gamma^k zeta_0, 0 < gamma <= 1      */
-    double  eps;         /* stop when e_k <= eps                                    */
+    double  eps;         /* stop when e_k <= eps (eps < 0: run max_iter iterations) */
     int32_t max_iter;    /* iteration cap, >= 1                                     */
     uint64_t seed;       /* index-sampler seed (SplitMix64 stream, see below)       */
     double  svd_tol;     /* relative residual tolerance of the top-r SVD; 0: default
@@ -163,7 +163,7 @@ int ircur_get_core(ircur_ctx* ctx, double* M_dev, double* W_dev,
 
 /*
  * Output of Algorithm 1 for the last completed iteration k: C_k (n1 x sJ),
- * U_k^+ (sJ x sI) and R_k (n1 x ... sI x n2), and optionally the sparse
+ * U_k^+ (sJ x sI) and R_k (sI x n2), and optionally the sparse
  * blocks S_I = [S_k]_{I,:} (sI x n2) and S_J = [S_k]_{:,J} (n1 x sJ), all in
  * the factor dtype (device).  Any pointer may be NULL.  Asynchronous.
  */
@@ -218,6 +218,13 @@ int ircur_get_info(ircur_ctx* ctx, int32_t* svd_iters, double* svd_resid,
  */
 int ircur_sample(uint64_t seed, int64_t t, int64_t n1, int64_t n2, int32_t sI,
                  int32_t sJ, int32_t* I_host, int32_t* J_host);
+
+/*
+ * Accumulated phase times (microseconds) of the SVD kernel's first
+ * workgroup, 16 slots, for builds compiled with IRCUR_PHASE_PROFILE (zeros
+ * otherwise).  Synchronises.
+ */
+int ircur_get_phase_profile(ircur_ctx* ctx, double* us16);
 
 void        ircur_destroy(ircur_ctx* ctx);
 const char* ircur_strerror(int status);

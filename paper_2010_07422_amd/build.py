@@ -36,15 +36,17 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
-    """Compile every HIP source to an object and link libircur.so."""
+def build(verbose: bool = False, jobs: int = 3, out: str | None = None,
+          defines: tuple = ()) -> str:
+    """Compile every HIP source to an object and link libircur.so (or `out`)."""
     from concurrent.futures import ThreadPoolExecutor
-    objdir = os.path.join(PKG, "_build")
+    lib_path = out or LIB
+    objdir = os.path.join(PKG, "_build" if not defines else "_build_" + "_".join(defines))
     os.makedirs(objdir, exist_ok=True)
 
     def comp(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *("-D" + d for d in defines), "-c", os.path.join(CSRC, src), "-o", obj]
         out = _run(cmd)
         if verbose and out.strip():
             print(out)
@@ -52,10 +54,10 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(comp, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

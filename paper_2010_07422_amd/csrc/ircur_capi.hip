@@ -48,21 +48,28 @@ SplitMix64 index_stream(uint64_t seed, int64_t t) {
     return SplitMix64{sm_mix(key)};
 }
 
-// k distinct values of [0, n), ascending.  Membership via a sorted vector is
-// enough for the sizes here (k is a few hundred to a few thousand).
+// k distinct values of [0, n), ascending (Floyd's algorithm).  Membership is
+// a bitmap over [0, n) (cleared per call), so a draw costs O(k + n/64).
 void floyd(SplitMix64& g, int64_t n, int32_t k, int32_t* out) {
-    std::vector<int64_t> chosen;
-    chosen.reserve(k);
+    static thread_local std::vector<uint64_t> bits;
+    const size_t words = (size_t)((n + 63) / 64);
+    bits.assign(words, 0ull);
     for (int64_t j = n - k; j < n; ++j) {
         const int64_t t = (int64_t)g.below((uint64_t)(j + 1));
-        auto it = std::lower_bound(chosen.begin(), chosen.end(), t);
-        if (it != chosen.end() && *it == t) {
-            chosen.insert(std::lower_bound(chosen.begin(), chosen.end(), j), j);
-        } else {
-            chosen.insert(it, t);
+        uint64_t& w = bits[(size_t)(t >> 6)];
+        const uint64_t m = 1ull << (t & 63);
+        if (w & m) bits[(size_t)(j >> 6)] |= 1ull << (j & 63);
+        else w |= m;
+    }
+    int32_t o = 0;
+    for (size_t wi = 0; wi < words && o < k; ++wi) {
+        uint64_t w = bits[wi];
+        while (w) {
+            const int b = __builtin_ctzll(w);
+            out[o++] = (int32_t)(wi * 64 + b);
+            w &= w - 1;
         }
     }
-    for (int32_t i = 0; i < k; ++i) out[i] = (int32_t)chosen[i];
 }
 
 constexpr int kChunk = 32;        // iterations per enqueue batch
@@ -161,7 +168,7 @@ int validate(const ircur_params* p, const void* D, const void* Dt, int64_t ldDt)
     if (p->err_mode != 0 && p->err_mode != 1) return IRCUR_ERR_ARG;
     if (!(p->zeta0 >= 0.0) || std::isnan(p->zeta0)) return IRCUR_ERR_ARG;
     if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return IRCUR_ERR_ARG;
-    if (!(p->eps >= 0.0)) return IRCUR_ERR_ARG;
+    if (std::isnan(p->eps)) return IRCUR_ERR_ARG;
     if (p->max_iter < 1) return IRCUR_ERR_ARG;
     if (!(p->svd_tol >= 0.0) || p->svd_max_it < 0) return IRCUR_ERR_ARG;
     if (p->svd_block != 0 &&
@@ -305,6 +312,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.Zp = c->Zp; sa.Gp = c->Gp; sa.Tp = c->Tp;
     sa.W = c->W; sa.V = c->V; sa.sigma = c->sigma;
     sa.rowI = c->rowI; sa.rowJ = c->rowJ; sa.GmI = c->GmI; sa.GmJ = c->GmJ; sa.scaleJ = c->scaleJ;
+    sa.qs = row_stride(c->R, (int)c->fsz);
     sa.info = c->info + k; sa.st = c->st;
     HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
     c->have_prevV = true;
@@ -432,12 +440,19 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->R = pad_rank(p.r);
     const int smin = std::min(p.sI, p.sJ);
     int pb = p.svd_block ? p.svd_block : std::min(std::min(smin, 32), p.r + std::max(4, p.r / 2));
-    c->G = std::max(1, std::min(8, (p.sI + 15) / 16));
-    c->bs = (p.sI + c->G - 1) / c->G;
-    size_t lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
-    while (lds > 160 * 1024 && pb > p.r) {
+    // SVD workgroups: the fewest of 8, 16, 32 whose LDS layout (M row block,
+    // subspace blocks) fits in 160 KiB; then shrink the subspace if needed.
+    size_t lds = 0;
+    for (;;) {
+        bool ok = false;
+        for (int g : {8, 16, 32}) {
+            c->G = g;
+            c->bs = (p.sI + g - 1) / g;
+            lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
+            if (lds <= 160 * 1024) { ok = true; break; }
+        }
+        if (ok || pb <= p.r) break;
         --pb;
-        lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
     }
     if (lds > 160 * 1024) { delete c; return IRCUR_ERR_UNSUPPORTED; }
     c->psvd = pb;
@@ -487,8 +502,11 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     TRY(dalloc(c, &c->W, (size_t)p.sI * R));
     TRY(dalloc(c, &c->V, (size_t)p.sJ * R));
     TRY(dalloc(c, &c->sigma, R));
-    TRY(dalloc_bytes(c, &c->rowI, (size_t)p.sI * 3 * R * c->fsz));
-    TRY(dalloc_bytes(c, &c->rowJ, (size_t)p.sJ * 3 * R * c->fsz));
+    const size_t qs = (size_t)row_stride(c->R, (int)c->fsz);
+    TRY(dalloc_bytes(c, &c->rowI, (size_t)p.sI * qs * c->fsz));
+    TRY(dalloc_bytes(c, &c->rowJ, (size_t)p.sJ * qs * c->fsz));
+    HIPCHK(c, hipMemset(c->rowI, 0, (size_t)p.sI * qs * c->fsz));
+    HIPCHK(c, hipMemset(c->rowJ, 0, (size_t)p.sJ * qs * c->fsz));
     TRY(dalloc_bytes(c, &c->GmI, R * R * c->fsz));
     TRY(dalloc_bytes(c, &c->GmJ, R * R * c->fsz));
     TRY(dalloc_bytes(c, &c->scaleJ, R * c->fsz));
@@ -741,6 +759,14 @@ int ircur_set_state(ircur_ctx* c, const void* buf, size_t bytes) {
     c->acc_next = k;
     c->stopped = hdr[2] != 0;
     c->have_prevV = false;
+    return IRCUR_OK;
+}
+
+int ircur_get_phase_profile(ircur_ctx* c, double* us16) {
+    if (!c || !us16) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    for (int i = 0; i < 16; ++i) us16[i] = (double)c->st_host->phase[i] * 0.01;   // 100 MHz ticks
     return IRCUR_OK;
 }
 

@@ -14,6 +14,15 @@ constexpr int kRanks[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
 // the pass kernel reads up to this many indices past the rows it uses.
 constexpr int kIndexPad = 16;
 
+// Row stride (elements) of the per-row data of the pass: 3R rounded up to a
+// multiple of 16 bytes.
+template <typename F, int R> struct RowStride {
+    static constexpr int value = ((3 * R * (int)sizeof(F) + 15) / 16) * (16 / (int)sizeof(F));
+};
+inline int row_stride(int R, int fsz) { return ((3 * R * fsz + 15) / 16) * (16 / fsz); }
+// LDS budget of the pass kernel's per-row data stage.
+constexpr int kPassStageBytes = 96 * 1024;
+
 inline int pad_rank(int r) {
     for (int v : kRanks) if (v >= r) return v;
     return -1;
@@ -31,6 +40,7 @@ struct DevState {
     double e_last;
     uint32_t bar_ctr;    // grid-barrier counter of the SVD kernel
     uint32_t pad_;
+    uint64_t phase[16];  // phase timers (100 MHz ticks), only with IRCUR_PHASE_PROFILE
 };
 
 // Per-iteration SVD diagnostics, one record per iteration.
@@ -51,8 +61,8 @@ struct SideArgs {
     int32_t s;
     int64_t n;             // row length (n2 or n1)
     const void* P;         // B_k (side 0) or A_k^T (side 1): R x n, row stride n
-    const void* rowdata;   // s x 3R: [gathered factor | projection | prediction]
-    const void* Gm;        // R x R correction matrix for the residual
+    const void* rowdata;   // s x QS (QS = row_stride): [gathered factor | projection | Delta]
+    const void* Gm;        // R x R: Gamma (side 0) or Gamma'^T (side 1)
     const void* outscale;  // R scales of the output (nullptr: 1)
     void* out;             // new factor, R x n, row stride n
     double* part;          // 2 doubles per workgroup: (residual, ||D_side||^2)
@@ -64,6 +74,7 @@ struct PassArgs {
     double zeta;           // threshold zeta_{k+1}
     float zeta_f;          // largest float <= zeta (exact float comparison)
     int32_t err_mode;
+    int32_t segmax;        // rows per wave per LDS stage (set by the launcher)
     const DevState* st;
 };
 
@@ -100,8 +111,9 @@ struct SvdArgs {
     double* W;             // sI x R out
     double* V;             // sJ x R out
     double* sigma;         // R out
-    void* rowI;            // sI x 3R (factor dtype)
-    void* rowJ;            // sJ x 3R
+    void* rowI;            // sI x qs (factor dtype)
+    void* rowJ;            // sJ x qs
+    int32_t qs;            // row stride of rowI / rowJ (elements)
     void* GmI;             // R x R
     void* GmJ;             // R x R
     void* scaleJ;          // R

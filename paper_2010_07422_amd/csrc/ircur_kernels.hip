@@ -8,6 +8,17 @@
 //   pass:  row side   R = [D - S_{k+1}]_{I,:},  B_{k+1} = W_r^T R            (eq. (2), (3))
 //          column side C = [D - S_{k+1}]_{:,J}, A_{k+1} = C V_r Sigma_r^+
 //          plus the partial sums of the stopping criterion (eq. (6)).
+//
+// The pass works with the small quantity xr = v - (L_k)_ij, which is x where
+// the entry is kept and 0 where it is thresholded (up to rounding), so that
+// both the new factor and the residual of eq. (6) are formed without
+// cancellation:
+//   row side   g_j = W_r^T xr[:, j],  B_{k+1}[:, j] = Gamma B_k[:, j] + g_j,
+//              Gamma = W_r^T A_k[I, :]  (so W_r^T R = Gamma B_k + g);
+//              z = xr + Delta_a . B_k[:, j],  Delta = (I - W_r W_r^T) A_k[I, :],
+//              so z = R - W_r Gamma B_k[:, j] and
+//              ||R[:, j] - W_r B_{k+1}[:, j]||^2 = ||z||^2 - ||g_j||^2;
+//   column side is the same with (A_k^T, J, V_r, Gamma' = B_k[:, J] V_r).
 //   final: e_{k+1} and the device-side stop flag.
 //
 // Every element of a sampled row or column is computed as
@@ -18,6 +29,8 @@
 #include "ircur_internal.h"
 
 #include <stdint.h>
+
+#include <algorithm>
 
 namespace ircur {
 
@@ -111,11 +124,13 @@ __global__ __launch_bounds__(256) void core_kernel(CoreArgs a) {
 // ----------------------------------------------------------------- pass ---
 
 // One workgroup: 64 consecutive outputs (one per lane) x all s gathered rows.
-// Wave w takes a contiguous quarter of the rows and keeps U row loads in
+// Wave w takes a contiguous quarter of the rows and keeps U row loads of D in
 // flight (the next group is issued before the current one is consumed); the
-// four partial sums are reduced in LDS at the end.  Per-row data (gathered
-// factor row, projection row, prediction row) is wave-uniform and read
-// through the scalar unit.  The index arrays carry kIndexPad valid trailing
+// four partial sums are reduced in LDS at the end.  The per-row data
+// (gathered factor row, projection row, Delta row; QS elements per row, 16-byte
+// aligned) is wave-uniform: the workgroup stages it in LDS with batched
+// 16-byte loads (all rows at once unless they exceed the LDS budget) and reads
+// it back as broadcast loads.  The index arrays carry kIndexPad valid trailing
 // entries, so a group may read past the end of a wave's rows.
 template <typename T> struct RowsInFlight { static constexpr int value = 8; };
 template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
@@ -123,8 +138,11 @@ template <> struct RowsInFlight<double> { static constexpr int value = 4; };
 
 template <typename T, typename F, int R, bool LIT>
 __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta, float zeta_f,
-                                          F (*red)[R][64], double (*redz)[64], double (*redd)[64]) {
+                                          F (*red)[R][64], double (*redz)[64], double (*redd)[64],
+                                          F* qstage, int segmax) {
     constexpr int U = RowsInFlight<T>::value;
+    constexpr int QS = RowStride<F, R>::value;
+    constexpr int UPR = QS * (int)sizeof(F) / 16;          // 16-byte units per row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t col = (int64_t)wg * 64 + lane;
@@ -132,7 +150,7 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     const int64_t n = S.n;
     const T* __restrict__ X = (const T*)S.X;
     const F* __restrict__ P = (const F*)S.P;
-    const F* __restrict__ rd = (const F*)S.rowdata;
+    const uint4* __restrict__ rd4 = (const uint4*)S.rowdata;
     const int32_t* __restrict__ rows = S.rows;
     const int64_t ldX = S.ldX;
 
@@ -147,12 +165,46 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     const int chunk = (S.s + 3) >> 2;
     const int a_begin = wave * chunk;
     const int a_end = min(S.s, a_begin + chunk);
+    // rows per stage: whole chunk if it fits, else segmax (a multiple of U)
+    const int SEG = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    F* __restrict__ qw = qstage + wave * (SEG * QS);
 
+    F dv[U];
     if (a_end > a_begin) {
-        F dv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) dv[u] = ld<T, F>(Xc + (int64_t)rows[a_begin + u] * ldX);
-        for (int a0 = a_begin; a0 < a_end; a0 += U) {
+    }
+    for (int seg0 = 0; seg0 < chunk; seg0 += SEG) {       // uniform over the workgroup
+        const int sb = a_begin + seg0;
+        const int se = min(a_end, sb + SEG);
+        __syncthreads();                                  // previous segment consumed
+        {
+            const int units = 4 * SEG * UPR;
+            for (int base = threadIdx.x; base < units; base += 256 * 8) {
+                uint4 v[8];
+                int dst[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int un = base + u * 256;
+                    dst[u] = -1;
+                    if (un < units) {
+                        const int w = un / (SEG * UPR);
+                        const int rem = un - w * (SEG * UPR);
+                        const int rr = rem / UPR, kk = rem - rr * UPR;
+                        const int row = w * chunk + seg0 + rr;
+                        if (seg0 + rr < chunk && row < S.s) {
+                            v[u] = rd4[(int64_t)row * UPR + kk];
+                            dst[u] = un;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dst[u] >= 0) ((uint4*)qstage)[dst[u]] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int a0 = sb; a0 < se; a0 += U) {
             F cur[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u] = dv[u];
@@ -163,27 +215,25 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int a = a0 + u;
-                if (a < a_end) {
-                const F d = valid ? cur[u] : F(0);
-                const F* __restrict__ q = rd + (int64_t)a * (3 * R);
-                F dot = F(0);
+                if (a < se) {
+                    const F d = valid ? cur[u] : F(0);
+                    const F* q = qw + (a - sb) * QS;
+                    F dot = F(0);
 #pragma unroll
-                for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c], dot);
-                bool o;
-                const F v = entry_value<F>(d, dot, zeta, zeta_f, &o);
+                    for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c], dot);
+                    const F x = d - dot;
+                    const F xr = above(x < F(0) ? -x : x, zeta, zeta_f) ? F(0) : x;
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] = fmaT(q[R + c], v, acc[c]);
-                if (LIT) {
-                    F pr = F(0);
+                    for (int c = 0; c < R; ++c) acc[c] = fmaT(q[R + c], xr, acc[c]);
+                    if (LIT) {
+                        F z = xr;
 #pragma unroll
-                    for (int c = 0; c < R; ++c) pr = fmaT(q[2 * R + c], p[c], pr);
-                    const F z = v - pr;
-                    zz = fmaT(z, z, zz);
-                } else {
-                    const F xr = o ? F(0) : (d - dot);
-                    zz = fmaT(xr, xr, zz);
-                }
-                dd = fmaT(d, d, dd);
+                        for (int c = 0; c < R; ++c) z = fmaT(q[2 * R + c], p[c], z);
+                        zz = fmaT(z, z, zz);
+                    } else {
+                        zz = fmaT(xr, xr, zz);
+                    }
+                    dd = fmaT(d, d, dd);
                 }
             }
         }
@@ -201,15 +251,13 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
         double corr = 0.0;
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const F sum = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
-            if (LIT) {
-                F g = F(0);
+            const F g = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+            if (LIT) corr = __builtin_fma((double)g, (double)g, corr);
+            F base = F(0);
 #pragma unroll
-                for (int e = 0; e < R; ++e) g = fmaT(Gm[c * R + e], p[e], g);
-                const double dg = (double)(sum - g);
-                corr = __builtin_fma(dg, dg, corr);
-            }
-            if (valid) out[c * n + col] = sc ? sum * sc[c] : sum;
+            for (int e = 0; e < R; ++e) base = fmaT(Gm[c * R + e], p[e], base);
+            const F val = base + g;
+            if (valid) out[c * n + col] = sc ? val * sc[c] : val;
         }
         double zl = ((redz[0][lane] + redz[1][lane]) + redz[2][lane]) + redz[3][lane];
         double dl = ((redd[0][lane] + redd[1][lane]) + redd[2][lane]) + redd[3][lane];
@@ -229,11 +277,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
     __shared__ F red[4][R][64];
     __shared__ double redz[4][64];
     __shared__ double redd[4][64];
+    extern __shared__ __align__(16) unsigned char dyn[];
+    F* qstage = (F*)dyn;
     const int wg = blockIdx.x;
     if (wg < a.side[0].nwg)
-        side_body<T, F, R, LIT>(a.side[0], wg, a.zeta, a.zeta_f, red, redz, redd);
+        side_body<T, F, R, LIT>(a.side[0], wg, a.zeta, a.zeta_f, red, redz, redd, qstage, a.segmax);
     else
-        side_body<T, F, R, LIT>(a.side[1], wg - a.side[0].nwg, a.zeta, a.zeta_f, red, redz, redd);
+        side_body<T, F, R, LIT>(a.side[1], wg - a.side[0].nwg, a.zeta, a.zeta_f, red, redz, redd, qstage,
+                                a.segmax);
 }
 
 // ------------------------------------------------------------- finalize ---
@@ -290,10 +341,27 @@ static hipError_t core_r(const CoreArgs& a, hipStream_t s) {
 }
 
 template <typename T, typename F, int R>
-static hipError_t pass_r(const PassArgs& a, hipStream_t s) {
+static hipError_t pass_r(const PassArgs& a0, hipStream_t s) {
+    PassArgs a = a0;
+    constexpr int U = RowsInFlight<T>::value;
+    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
+    int segmax = (kPassStageBytes / (4 * rowbytes)) / U * U;
+    if (segmax < U) segmax = U;
+    const int chunk = (std::max(a.side[0].s, a.side[1].s) + 3) / 4;
+    const int seg = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    a.segmax = segmax;
+    const size_t lds = (size_t)4 * seg * rowbytes;
+    static bool attr[2] = {false, false};
+    const int li = a.err_mode == 0 ? 0 : 1;
+    const void* fn = a.err_mode == 0 ? (const void*)pass_kernel<T, F, R, true> : (const void*)pass_kernel<T, F, R, false>;
+    if (!attr[li]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kPassStageBytes);
+        if (e != hipSuccess) return e;
+        attr[li] = true;
+    }
     const unsigned grid = (unsigned)(a.side[0].nwg + a.side[1].nwg);
-    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 256, 0, s>>>(a);
-    else pass_kernel<T, F, R, false><<<grid, 256, 0, s>>>(a);
+    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 256, lds, s>>>(a);
+    else pass_kernel<T, F, R, false><<<grid, 256, lds, s>>>(a);
     return hipGetLastError();
 }
 

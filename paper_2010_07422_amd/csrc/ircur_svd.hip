@@ -19,9 +19,10 @@
 // or B_k[:, J]^T (resampled sets), completed with pseudo-random columns.
 //
 // The epilogue also builds the per-row data of the fused pass: for each
-// sampled row a, [A_k[I_a, :] | W_r[a, :] | (W_r Gamma)[a, :]] with
-// Gamma = W_r^T A_k[I, :]; for each sampled column b,
-// [B_k[:, J_b] | V_r[b, :] | (Gamma' V_r^T)[:, b]] with Gamma' = B_k[:, J] V_r.
+// sampled row a, [A_k[I_a, :] | W_r[a, :] | Delta[a, :]] with
+// Delta = A_k[I, :] - W_r Gamma and Gamma = W_r^T A_k[I, :]; for each sampled
+// column b, [B_k[:, J_b] | V_r[b, :] | Delta'[b, :]] with
+// Delta'[b, :] = B_k[:, J_b] - Gamma' V_r[b, :]^T and Gamma' = B_k[:, J] V_r.
 #include "ircur_internal.h"
 
 #include <stdint.h>
@@ -213,19 +214,24 @@ __device__ void jacobi_eig(double* A, int p, double* E, double* lam, double* cs,
     const int pe = p + (p & 1);
     const int half = pe / 2;
     for (int sweep = 0; sweep < 40; ++sweep) {
+        // converged when every off-diagonal entry is negligible against its
+        // diagonal pair or against the largest diagonal entry
+        double dmax = 0.0;
+        for (int i = tid; i < p; i += NT) dmax = fmax(dmax, fabs(A[i * p + i]));
+        dmax = block_max(dmax, red);
         double off = 0.0;
         for (int e = tid; e < p * p; e += NT) {
             const int i = e / p, j = e - i * p;
             if (i < j) {
-                const double aij = A[e];
-                if (aij != 0.0) {
-                    const double den = __builtin_sqrt(fabs(A[i * p + i] * A[j * p + j]));
-                    off = fmax(off, den > 0.0 ? fabs(aij) / den : 1.0);
-                }
+                const double aij = fabs(A[e]);
+                // below the rounding level of the largest entry nothing is left to do
+                if (aij > 1e-15 * __builtin_sqrt(fabs(A[i * p + i] * A[j * p + j])) &&
+                    aij > (double)p * 2.220446049250313e-16 * dmax)
+                    off = 1.0;
             }
         }
         off = block_max(off, red);
-        if (!(off > 1e-15)) break;
+        if (!(off > 0.0)) break;
         for (int rnd = 0; rnd < pe - 1; ++rnd) {
             if (tid < half) {
                 int i, j;
@@ -236,7 +242,8 @@ __device__ void jacobi_eig(double* A, int p, double* E, double* lam, double* cs,
                 if (j < p) {
                     const double aij = A[i * p + j];
                     const double aii = A[i * p + i], ajj = A[j * p + j];
-                    if (aij != 0.0 && fabs(aij) > 1e-17 * __builtin_sqrt(fabs(aii * ajj))) {
+                    if (fabs(aij) > 1e-17 * __builtin_sqrt(fabs(aii * ajj)) && fabs(aij) > 1e-300 &&
+                        fabs(aij) > 1e-3 * 2.220446049250313e-16 * (fabs(aii) + fabs(ajj))) {
                         const double tau = (ajj - aii) / (2.0 * aij);
                         double t;
                         if (fabs(tau) > 1e150) t = 0.5 / tau;
@@ -304,9 +311,10 @@ __device__ void jacobi_eig(double* A, int p, double* E, double* lam, double* cs,
 size_t svd_lds_bytes(int sJ, int p, int bs, int R) {
     const int pw = p > R ? p : R;
     size_t d = 0;
-    d += (size_t)sJ * pw;         // Q (later: staged B_k[:, J])
-    d += (size_t)sJ * pw;         // Z (later: V_r)
-    d += (size_t)bs * pw;         // Y block (later: W block)
+    d += (size_t)bs * sJ;         // M block
+    d += (size_t)sJ * pw;         // Q (later: V_r)
+    d += (size_t)sJ * pw;         // Z (later: staged B_k[:, J])
+    d += (size_t)bs * pw;         // Y block
     d += 4 * (size_t)p * p;       // Gr, E, L, tmp
     d += 4 * PMAX;                // lam, dinv, cs
     d += NT;                      // red
@@ -314,86 +322,160 @@ size_t svd_lds_bytes(int sJ, int p, int bs, int R) {
     d += (size_t)bs * R;          // staged A_k[I_blk, :]
     d += (size_t)bs * R;          // W block
     size_t bytes = d * sizeof(double);
-    bytes += (2 * PMAX + 8) * sizeof(int);
+    bytes += (size_t)(sJ + bs + 2 * PMAX) * sizeof(int);
     return bytes;
 }
 
+namespace {
+
+// Loads of a gather loop are issued in batches of 8 per thread before any of
+// them is consumed, so a batch costs one memory latency.
+template <typename LoadF, typename StoreF>
+__device__ __forceinline__ void batched(int total, LoadF load, StoreF store) {
+    for (int base = threadIdx.x; base < total; base += NT * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + u * NT;
+            v[u] = e < total ? load(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = base + u * NT;
+            if (e < total) store(e, v[u]);
+        }
+    }
+}
+
+// out[e] = sum_g src[g * stride + e] for e < total, g in a fixed order; the
+// G loads of an element are independent and issued together.
+template <int G>
+__device__ __forceinline__ void reduce_parts(const double* __restrict__ src, size_t stride, int total,
+                                             double* out) {
+    for (int e = threadIdx.x; e < total; e += NT) {
+        double v[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = src[(size_t)g * stride + e];
+        double s = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) s += v[g];
+        out[e] = s;
+    }
+}
+
+}  // namespace
+
+#ifdef IRCUR_PHASE_PROFILE
+#define PHASE(i)                                                              \
+    do {                                                                      \
+        if (blockIdx.x == 0 && threadIdx.x == 0) {                            \
+            const uint64_t t_ = __builtin_amdgcn_s_memrealtime();             \
+            a.st->phase[i] += t_ - t_prev;                                    \
+            t_prev = t_;                                                      \
+        }                                                                     \
+    } while (0)
+#else
+#define PHASE(i) do { } while (0)
+#endif
+
+template <int G>
 __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
     if (a.st->stop) return;
+#ifdef IRCUR_PHASE_PROFILE
+    uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
+#endif
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
-    const int sI = a.sI, sJ = a.sJ, p = a.p, r = a.r, R = a.R, G = a.G;
+    const int sI = a.sI, sJ = a.sJ, p = a.p, r = a.r, R = a.R;
     const int pw = p > R ? p : R;
     const int wg = blockIdx.x;
-    const int a0 = wg * a.bs;
+    const int bsz = a.bs;
+    const int a0 = wg * bsz;
     int nb = sI - a0;
-    if (nb > a.bs) nb = a.bs;
+    if (nb > bsz) nb = bsz;
     if (nb < 0) nb = 0;
 
-    double* Q = smem;
+    double* Mb = smem;                          // nb x sJ
+    double* Q = Mb + (size_t)bsz * sJ;
     double* Z = Q + (size_t)sJ * pw;
     double* Y = Z + (size_t)sJ * pw;
-    double* Gr = Y + (size_t)a.bs * pw;
+    double* Gr = Y + (size_t)bsz * pw;
     double* E = Gr + p * p;
     double* L = E + p * p;
     double* tmp = L + p * p;
     double* lam = tmp + p * p;
     double* dinv = lam + PMAX;
-    double* cs = dinv + PMAX;          // 2*PMAX/2 entries used
+    double* cs = dinv + PMAX;
     double* red = cs + 2 * PMAX;
-    double* gam = red + NT;            // R x R
-    double* gam2 = gam + R * R;        // R x R
-    double* Ast = gam2 + R * R;        // bs x R
-    double* Wb = Ast + (size_t)a.bs * R; // bs x R
-    int* ibuf = (int*)(Wb + (size_t)a.bs * R);
-    int* dead = ibuf;                  // PMAX
-    int* pidx = ibuf + PMAX;           // PMAX
-
+    double* gam = red + NT;                     // R x R
+    double* gam2 = gam + R * R;                 // R x R
+    double* Ast = gam2 + R * R;                 // bs x R
+    double* Wb = Ast + (size_t)bsz * R;         // bs x R
+    int* Jl = (int*)(Wb + (size_t)bsz * R);     // sJ
+    int* Il = Jl + sJ;                          // bs
+    int* dead = Il + bsz;                       // PMAX
+    int* pidx = dead + PMAX;                    // PMAX
 
     uint32_t nbar = 0;
-    const double* M = a.M;
     const int64_t n1 = a.n1, n2 = a.n2;
-    // factor dtype: encoded in the high bit of warm (set by the launcher)
     const int fd = (a.warm >> 8) & 1;   // 0: double factors, 1: float factors
     const int warm = a.warm & 0xff;
+    const double* __restrict__ Mg = a.M;
 
-    // ---- warm start -------------------------------------------------------
-    for (int e = tid; e < sJ * p; e += NT) {
-        const int b = e / p, c = e - b * p;
-        double v;
-        if (warm == 1) v = a.prevV[e];
-        else if (warm == 2 && c < r) v = fget(a.B, (int64_t)c * n2 + a.J[b], fd);
-        else v = rnd_unit(a.salt, (uint64_t)e);
-        Q[e] = v;
+    // ---- stage indices and the M block; warm start --------------------------
+    for (int b = tid; b < sJ; b += NT) Jl[b] = a.J[b];
+    for (int ar = tid; ar < nb; ar += NT) Il[ar] = a.I[a0 + ar];
+    batched(nb * sJ, [&](int e) { return Mg[(size_t)a0 * sJ + e]; }, [&](int e, double v) { Mb[e] = v; });
+    __syncthreads();
+    if (warm == 1) {
+        batched(sJ * p, [&](int e) { return a.prevV[e]; }, [&](int e, double v) { Q[e] = v; });
+    } else {
+        batched(sJ * p,
+                [&](int e) {
+                    const int b = e / p, c = e - b * p;
+                    if (warm == 2 && c < r) return fget(a.B, (int64_t)c * n2 + Jl[b], fd);
+                    return rnd_unit(a.salt, (uint64_t)e);
+                },
+                [&](int e, double v) { Q[e] = v; });
     }
     __syncthreads();
+    PHASE(0);
     cholqr2(Q, sJ, p, Gr, L, dinv, dead, red, a.salt + 17);
+    PHASE(1);
 
     int it = 0;
     bool conv = false;
     double maxres = 0.0;
     for (;;) {
-        // Y_blk = M_blk Q
+        // Y_blk = M_blk Q   (two rows per thread item, both from LDS)
         for (int e = tid; e < nb * p; e += NT) {
             const int ar = e / p, c = e - ar * p;
-            const double* mrow = M + (int64_t)(a0 + ar) * sJ;
-            double s0 = 0.0, s1 = 0.0;
+            const double* mrow = Mb + (size_t)ar * sJ;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
             int b = 0;
-            for (; b + 1 < sJ; b += 2) {
+            for (; b + 3 < sJ; b += 4) {
                 s0 = __builtin_fma(mrow[b], Q[b * p + c], s0);
                 s1 = __builtin_fma(mrow[b + 1], Q[(b + 1) * p + c], s1);
+                s2 = __builtin_fma(mrow[b + 2], Q[(b + 2) * p + c], s2);
+                s3 = __builtin_fma(mrow[b + 3], Q[(b + 3) * p + c], s3);
             }
-            if (b < sJ) s0 = __builtin_fma(mrow[b], Q[b * p + c], s0);
-            Y[ar * p + c] = s0 + s1;
+            for (; b < sJ; ++b) s0 = __builtin_fma(mrow[b], Q[b * p + c], s0);
+            Y[ar * p + c] = (s0 + s1) + (s2 + s3);
         }
         __syncthreads();
+        PHASE(2);
         // Z partial = M_blk^T Y_blk, Gram partial = Y_blk^T Y_blk
         double* Zp = a.Zp + (size_t)wg * sJ * p;
         for (int e = tid; e < sJ * p; e += NT) {
             const int b = e / p, c = e - b * p;
-            double s = 0.0;
-            for (int ar = 0; ar < nb; ++ar) s = __builtin_fma(M[(int64_t)(a0 + ar) * sJ + b], Y[ar * p + c], s);
-            Zp[e] = s;
+            double s0 = 0.0, s1 = 0.0;
+            int ar = 0;
+            for (; ar + 1 < nb; ar += 2) {
+                s0 = __builtin_fma(Mb[(size_t)ar * sJ + b], Y[ar * p + c], s0);
+                s1 = __builtin_fma(Mb[(size_t)(ar + 1) * sJ + b], Y[(ar + 1) * p + c], s1);
+            }
+            if (ar < nb) s0 = __builtin_fma(Mb[(size_t)ar * sJ + b], Y[ar * p + c], s0);
+            Zp[e] = s0 + s1;
         }
         double* Gp = a.Gp + (size_t)wg * p * p;
         for (int e = tid; e < p * p; e += NT) {
@@ -402,19 +484,12 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
             for (int ar = 0; ar < nb; ++ar) s = __builtin_fma(Y[ar * p + i], Y[ar * p + j], s);
             Gp[e] = s;
         }
+        PHASE(3);
         ++nbar;
         grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
-        // reduce in a fixed order
-        for (int e = tid; e < sJ * p; e += NT) {
-            double s = 0.0;
-            for (int g = 0; g < G; ++g) s += a.Zp[(size_t)g * sJ * p + e];
-            Z[e] = s;
-        }
-        for (int e = tid; e < p * p; e += NT) {
-            double s = 0.0;
-            for (int g = 0; g < G; ++g) s += a.Gp[(size_t)g * p * p + e];
-            Gr[e] = s;
-        }
+        PHASE(4);
+        reduce_parts<G>(a.Zp, (size_t)sJ * p, sJ * p, Z);
+        reduce_parts<G>(a.Gp, (size_t)p * p, p * p, Gr);
         __syncthreads();
         // symmetrise (partials are symmetric up to the summation order)
         for (int e = tid; e < p * p; e += NT) {
@@ -422,7 +497,9 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
             if (i < j) { const double v = 0.5 * (Gr[e] + Gr[j * p + i]); Gr[e] = v; Gr[j * p + i] = v; }
         }
         __syncthreads();
+        PHASE(5);
         jacobi_eig(Gr, p, E, lam, cs, pidx, tmp, red);
+        PHASE(6);
         ++it;
         // residual of the top r Ritz triplets
         const double lam0 = lam[0] > 0.0 ? lam[0] : 0.0;
@@ -442,22 +519,18 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
         }
         red[tid] = part;
         __syncthreads();
-        if (tid == 0) {
-            double mr = 0.0;
-            for (int i = 0; i < r; ++i) {
-                double s = 0.0;
-                for (int ch = 0; ch < nbp; ++ch) s += red[i * nbp + ch];
-                const double si = __builtin_sqrt(lam[i] > 0.0 ? lam[i] : 0.0);
-                double ri = 0.0;
-                if (si > negl && sig0 > 0.0) ri = __builtin_sqrt(s) / si / sig0;
-                mr = fmax(mr, ri);
-            }
-            tmp[0] = mr;
+        if (tid < r) {
+            double s = 0.0;
+            for (int ch = 0; ch < nbp; ++ch) s += red[tid * nbp + ch];
+            const double si = __builtin_sqrt(lam[tid] > 0.0 ? lam[tid] : 0.0);
+            tmp[tid] = (si > negl && sig0 > 0.0) ? __builtin_sqrt(s) / si / sig0 : 0.0;
         }
         __syncthreads();
-        maxres = tmp[0];
+        maxres = 0.0;
+        for (int i = 0; i < r; ++i) maxres = fmax(maxres, tmp[i]);
         __syncthreads();
         conv = !(maxres > a.tol);
+        PHASE(7);
         if (conv || it >= a.max_it) break;
         // Q <- orth(Z E)
         for (int e = tid; e < sJ * p; e += NT) {
@@ -468,36 +541,41 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
         }
         __syncthreads();
         cholqr2(Q, sJ, p, Gr, L, dinv, dead, red, a.salt + 1000003ull * (uint64_t)it);
+        PHASE(8);
     }
 
     // ---- epilogue ---------------------------------------------------------
     // sigma, keep rule (pinv: sigma_i > max(sI, sJ) * 2^-52 * sigma_1)
     const double sig0 = __builtin_sqrt(lam[0] > 0.0 ? lam[0] : 0.0);
     const double tolk = (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16 * sig0;
-    if (tid < PMAX) dinv[tid] = 0.0;      // reuse: 1/sigma for kept components
+    if (tid < PMAX) dinv[tid] = 0.0;      // 1/sigma for kept components
     __syncthreads();
     if (tid < r) {
         const double si = __builtin_sqrt(lam[tid] > 0.0 ? lam[tid] : 0.0);
         dinv[tid] = (sig0 > 0.0 && si > tolk) ? 1.0 / si : 0.0;
     }
-    __syncthreads();
-    // V (all p Ritz vectors) -> Z region as V_r (sJ x R, kept columns only),
-    // and the full Ritz basis to prevV_out (warm start of the next iteration)
+    // stage A_k[I_blk, :] and B_k[:, J] (independent gathers)
+    batched(nb * R, [&](int e) { const int ar = e / R, c = e - ar * R; return fget(a.At, (int64_t)c * n1 + Il[ar], fd); },
+            [&](int e, double v) { Ast[e] = v; });
+    // Ritz basis V = Q E: full basis to prevV_out (rows b % G == wg), kept
+    // columns to Z as V_r (sJ x R)
     for (int e = tid; e < sJ * p; e += NT) {
         const int b = e / p, c = e - b * p;
         double s = 0.0;
         for (int k = 0; k < p; ++k) s = __builtin_fma(Q[b * p + k], E[k * p + c], s);
         if ((b % G) == wg && a.prevV_out) a.prevV_out[e] = s;
-        Z[e] = s;        // overwritten below into the sJ x R layout
+        Z[e] = s;
     }
     __syncthreads();
-    // compact to V_r (sJ x R) in Q region (Q no longer needed)
+    double* Vr = Q;            // sJ x R (Q no longer needed)
     for (int e = tid; e < sJ * R; e += NT) {
         const int b = e / R, c = e - b * R;
-        Q[e] = (c < r && dinv[c] > 0.0) ? Z[b * p + c] : 0.0;
+        Vr[e] = (c < r && dinv[c] > 0.0) ? Z[b * p + c] : 0.0;
     }
     __syncthreads();
-    double* Vr = Q;            // sJ x R
+    double* Bst = Z;           // R x sJ
+    batched(R * sJ, [&](int e) { const int c = e / sJ, b = e - c * sJ; return fget(a.B, (int64_t)c * n2 + Jl[b], fd); },
+            [&](int e, double v) { Bst[e] = v; });
     // W block (nb x R): w_i = Y e_i / sigma_i for kept components
     for (int e = tid; e < nb * R; e += NT) {
         const int ar = e / R, c = e - ar * R;
@@ -507,17 +585,6 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
             s *= dinv[c];
         }
         Wb[e] = s;
-    }
-    __syncthreads();
-    // stage A_k[I_blk, :] and B_k[:, J]
-    for (int e = tid; e < nb * R; e += NT) {
-        const int ar = e / R, c = e - ar * R;
-        Ast[e] = fget(a.At, (int64_t)c * n1 + a.I[a0 + ar], fd);
-    }
-    double* Bst = Z;           // R x sJ
-    for (int e = tid; e < R * sJ; e += NT) {
-        const int c = e / sJ, b = e - c * sJ;
-        Bst[e] = fget(a.B, (int64_t)c * n2 + a.J[b], fd);
     }
     __syncthreads();
     // Gamma partial (R x R): sum_a W[a][i] A[I_a][c]
@@ -535,35 +602,33 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
         for (int b = 0; b < sJ; ++b) s = __builtin_fma(Bst[c * sJ + b], Vr[b * R + i], s);
         gam2[e] = s;
     }
+    PHASE(9);
     ++nbar;
     grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
-    for (int e = tid; e < R * R; e += NT) {
-        double s = 0.0;
-        for (int g = 0; g < G; ++g) s += a.Tp[(size_t)g * R * R + e];
-        gam[e] = s;
-    }
+    PHASE(10);
+    reduce_parts<G>(a.Tp, (size_t)R * R, R * R, gam);
     __syncthreads();
-    // rowI for this block: [A_k[I_a,:] | W[a,:] | (W Gamma)[a,:]]
+    // rowI for this block: [A_k[I_a,:] | W[a,:] | A_k[I_a,:] - (W Gamma)[a,:]]
     for (int e = tid; e < nb * R; e += NT) {
         const int ar = e / R, c = e - ar * R;
         double s = 0.0;
         for (int i = 0; i < R; ++i) s = __builtin_fma(Wb[ar * R + i], gam[i * R + c], s);
-        const int64_t base = (int64_t)(a0 + ar) * 3 * R;
+        const int64_t base = (int64_t)(a0 + ar) * a.qs;
         fput(a.rowI, base + c, Ast[e], fd);
         fput(a.rowI, base + R + c, Wb[e], fd);
-        fput(a.rowI, base + 2 * R + c, s, fd);
+        fput(a.rowI, base + 2 * R + c, Ast[e] - s, fd);
         a.W[(int64_t)(a0 + ar) * R + c] = Wb[e];
     }
-    // rowJ, rows b with b % G == wg: [B_k[:,J_b] | V[b,:] | (Gamma' V^T)[:, b]]
+    // rowJ, rows b with b % G == wg: [B_k[:,J_b] | V[b,:] | B_k[:,J_b] - (Gamma' V^T)[:, b]]
     for (int e = tid; e < sJ * R; e += NT) {
         const int b = e / R, c = e - b * R;
         if ((b % G) != wg) continue;
         double s = 0.0;
         for (int i = 0; i < R; ++i) s = __builtin_fma(gam2[c * R + i], Vr[b * R + i], s);
-        const int64_t base = (int64_t)b * 3 * R;
+        const int64_t base = (int64_t)b * a.qs;
         fput(a.rowJ, base + c, Bst[c * sJ + b], fd);
         fput(a.rowJ, base + R + c, Vr[e], fd);
-        fput(a.rowJ, base + 2 * R + c, s, fd);
+        fput(a.rowJ, base + 2 * R + c, Bst[c * sJ + b] - s, fd);
         a.V[e] = Vr[e];
     }
     if (wg == 0) {
@@ -588,15 +653,33 @@ __global__ __launch_bounds__(256) void svd_topr_kernel(SvdArgs a) {
             if (kept < r && sig0 > 0.0) a.st->rank_drop = 1;
         }
     }
+    PHASE(11);
 }
 
 hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s) {
     SvdArgs b = a;
     b.warm = (a.warm & 0xff) | ((dtype == 0 ? 0 : 1) << 8);
-    hipError_t e = hipFuncSetAttribute((const void*)svd_topr_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    svd_topr_kernel<<<a.G, NT, lds_bytes, s>>>(b);
+    const void* fn;
+    switch (a.G) {
+        case 8: fn = (const void*)svd_topr_kernel<8>; break;
+        case 16: fn = (const void*)svd_topr_kernel<16>; break;
+        case 32: fn = (const void*)svd_topr_kernel<32>; break;
+        default: return hipErrorInvalidValue;
+    }
+    // the attribute is raised once per instantiation to the 160 KiB maximum
+    static bool attr_set[3] = {false, false, false};
+    const int gi = a.G == 8 ? 0 : (a.G == 16 ? 1 : 2);
+    if (!attr_set[gi]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set[gi] = true;
+    }
+    (void)lds_bytes;
+    switch (a.G) {
+        case 8: svd_topr_kernel<8><<<8, NT, lds_bytes, s>>>(b); break;
+        case 16: svd_topr_kernel<16><<<16, NT, lds_bytes, s>>>(b); break;
+        default: svd_topr_kernel<32><<<32, NT, lds_bytes, s>>>(b); break;
+    }
     return hipGetLastError();
 }
 

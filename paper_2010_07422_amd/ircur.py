@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libircur.so")
+LIB_PATH = os.environ.get("IRCUR_LIBRARY") or os.path.join(_PKG, "libircur.so")
 
 OK, NOT_CONVERGED, WARN_RANK_DEFICIENT, WARN_SVD_INEXACT = 0, 1, 2, 3
 ERR_ARG, ERR_ALLOC, ERR_DEVICE, ERR_SVD, ERR_NONFINITE, ERR_STATE, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
@@ -66,6 +66,7 @@ _SIGS = {
     "ircur_get_info": (ctypes.c_int, [_P, _I32P, _DP, _DP, _I32P]),
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
+    "ircur_get_phase_profile": (ctypes.c_int, [_P, _DP]),
     "ircur_destroy": (None, [_P]),
     "ircur_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ircur_last_error": (ctypes.c_char_p, [_P]),
@@ -276,6 +277,11 @@ class IRCUR:
         cnt = ctypes.c_int64()
         self._check(lib().ircur_get_timing(self.h, ms, ctypes.byref(cnt)), "ircur_get_timing")
         return list(ms), cnt.value
+
+    def phase_profile(self):
+        buf = (ctypes.c_double * 16)()
+        self._check(lib().ircur_get_phase_profile(self.h, buf), "ircur_get_phase_profile")
+        return list(buf)
 
     def _sync_stream(self):
         import torch
