@@ -153,13 +153,15 @@ int ircur_get_history(ircur_ctx* ctx, double* e_host, int32_t cap,
 int ircur_get_sets(ircur_ctx* ctx, int32_t* I_host, int32_t* J_host);
 
 /*
- * Internals of the last completed iteration, for verification (device):
- * M_dev: [D - S_{k}]_{I,J} as double (sI x sJ); W_dev (sI x r), sigma_dev (r),
- * V_dev (sJ x r): the top-r SVD of M as double, dropped components zero.
- * Any pointer may be NULL.  Asynchronous.
+ * Internals of the last completed iteration, for verification (device), all
+ * double: M_dev = [D - S_k]_{I,J} (sI x sJ); Wt_dev (sI x r) and Q_dev
+ * (sJ x r), orthonormal bases of the top-r left and right singular subspaces
+ * of M; Kc_dev (r x r) with H_r(M) = Wt Kc Q^T, so the singular values of
+ * H_r(M) are those of Kc (section 3.1).  Dropped components are zero.  Any
+ * pointer may be NULL.  Asynchronous.
  */
-int ircur_get_core(ircur_ctx* ctx, double* M_dev, double* W_dev,
-                   double* sigma_dev, double* V_dev);
+int ircur_get_core(ircur_ctx* ctx, double* M_dev, double* Wt_dev,
+                   double* Kc_dev, double* Q_dev);
 
 /*
  * Output of Algorithm 1 for the last completed iteration k: C_k (n1 x sJ),

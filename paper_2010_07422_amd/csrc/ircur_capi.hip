@@ -104,9 +104,10 @@ struct ircur_ctx {
     int32_t* Ipin = nullptr;
     int32_t* Jpin = nullptr;
     double* M = nullptr;
+    double* MA = nullptr;
+    double* MB = nullptr;
     double* Zp = nullptr;
     double* Gp = nullptr;
-    double* Tp = nullptr;
     double* prevV = nullptr;
     double* W = nullptr;
     double* V = nullptr;
@@ -203,7 +204,7 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 
 void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
-                    c->M, c->Zp, c->Gp, c->Tp, c->prevV, c->W, c->V, c->sigma, c->rowI,
+                    c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
                     c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->part_row, c->part_col, c->st,
                     c->info, c->hist};
     for (void* b : bufs)
@@ -293,15 +294,15 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     CoreArgs ca{};
     ca.D = c->D; ca.ldD = p.ldD; ca.I = Id; ca.J = Jd; ca.sI = p.sI; ca.sJ = p.sJ;
     ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
-    ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.st = c->st;
+    ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.MA = c->MA; ca.MB = c->MB; ca.st = c->st;
     HIPCHK(c, launch_core(ca, p.dtype, c->R, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][1], s));
 
     SvdArgs sa{};
-    sa.M = c->M; sa.sI = p.sI; sa.sJ = p.sJ; sa.r = p.r; sa.R = c->R; sa.p = c->psvd;
+    sa.MA = c->MA; sa.MB = c->MB; sa.sI = p.sI; sa.sJ = p.sJ; sa.r = p.r; sa.R = c->R; sa.p = c->psvd;
     sa.G = c->G; sa.bs = c->bs;
     sa.max_it = p.svd_max_it > 0 ? p.svd_max_it : 64;
-    sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-12 : 1e-9);
+    sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : 1e-9);
     bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
                  std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
     sa.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
@@ -309,7 +310,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.prevV = c->prevV; sa.prevV_out = c->prevV;
     sa.I = Id; sa.J = Jd; sa.n1 = p.n1; sa.n2 = p.n2;
     sa.At = c->At[cur]; sa.B = c->B[cur];
-    sa.Zp = c->Zp; sa.Gp = c->Gp; sa.Tp = c->Tp;
+    sa.Zp = c->Zp; sa.Gp = c->Gp;
     sa.W = c->W; sa.V = c->V; sa.sigma = c->sigma;
     sa.rowI = c->rowI; sa.rowJ = c->rowJ; sa.GmI = c->GmI; sa.GmJ = c->GmJ; sa.scaleJ = c->scaleJ;
     sa.qs = row_stride(c->R, (int)c->fsz);
@@ -322,11 +323,11 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     PassArgs pa{};
     SideArgs& r0 = pa.side[0];
     r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
-    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outscale = nullptr; r0.out = c->B[nxt];
+    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outmat = nullptr; r0.out = c->B[nxt];
     r0.part = c->part_row; r0.nwg = c->nwg_row;
     SideArgs& r1 = pa.side[1];
     r1.X = c->Dt; r1.ldX = c->ldDt; r1.rows = Jd; r1.s = p.sJ; r1.n = p.n1; r1.P = c->At[cur];
-    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outscale = c->scaleJ; r1.out = c->At[nxt];
+    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outmat = c->scaleJ; r1.out = c->At[nxt];
     r1.part = c->part_col; r1.nwg = c->nwg_col;
     pa.zeta = zeta; pa.zeta_f = zf; pa.err_mode = p.err_mode; pa.st = c->st;
     HIPCHK(c, launch_pass(pa, p.dtype, c->R, s));
@@ -438,23 +439,21 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->p = *pin;
     const ircur_params& p = c->p;
     c->R = pad_rank(p.r);
-    const int smin = std::min(p.sI, p.sJ);
-    int pb = p.svd_block ? p.svd_block : std::min(std::min(smin, 32), p.r + std::max(4, p.r / 2));
-    // SVD workgroups: the fewest of 8, 16, 32 whose LDS layout (M row block,
-    // subspace blocks) fits in 160 KiB; then shrink the subspace if needed.
+    // SVD: tile width P >= R; workgroups G the fewest of 8, 16, 32 whose LDS
+    // layout (M row block, subspace blocks) fits in 160 KiB.
+    const int P = c->R <= 16 ? 16 : 32;
+    int pb = P;
     size_t lds = 0;
-    for (;;) {
+    {
         bool ok = false;
         for (int g : {8, 16, 32}) {
             c->G = g;
-            c->bs = (p.sI + g - 1) / g;
-            lds = svd_lds_bytes(p.sJ, pb, c->bs, c->R);
+            c->bs = 16 * ((p.sI + 16 * g - 1) / (16 * g));   // rows per workgroup, multiple of 16
+            lds = svd_lds_bytes(p.sJ, c->bs, P);
             if (lds <= 160 * 1024) { ok = true; break; }
         }
-        if (ok || pb <= p.r) break;
-        --pb;
+        if (!ok) { delete c; return IRCUR_ERR_UNSUPPORTED; }
     }
-    if (lds > 160 * 1024) { delete c; return IRCUR_ERR_UNSUPPORTED; }
     c->psvd = pb;
     c->svd_lds = lds;
     c->stream = (hipStream_t)stream;
@@ -495,13 +494,19 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         return IRCUR_ERR_ALLOC;
     }
     TRY(dalloc(c, &c->M, (size_t)p.sI * p.sJ));
+    {
+        const size_t sI16 = ((size_t)p.sI + 15) / 16 * 16, sJ16 = ((size_t)p.sJ + 15) / 16 * 16;
+        TRY(dalloc(c, &c->MA, sI16 * sJ16));
+        TRY(dalloc(c, &c->MB, sI16 * sJ16));
+        HIPCHK(c, hipMemset(c->MA, 0, sI16 * sJ16 * sizeof(double)));
+        HIPCHK(c, hipMemset(c->MB, 0, sI16 * sJ16 * sizeof(double)));
+    }
     TRY(dalloc(c, &c->Zp, (size_t)c->G * p.sJ * c->psvd));
-    TRY(dalloc(c, &c->Gp, (size_t)c->G * c->psvd * c->psvd));
-    TRY(dalloc(c, &c->Tp, (size_t)c->G * R * R));
-    TRY(dalloc(c, &c->prevV, (size_t)p.sJ * c->psvd));
+    TRY(dalloc(c, &c->Gp, (size_t)c->G * 2 * c->psvd * c->psvd));
+    TRY(dalloc(c, &c->prevV, (size_t)p.sJ * R));
     TRY(dalloc(c, &c->W, (size_t)p.sI * R));
     TRY(dalloc(c, &c->V, (size_t)p.sJ * R));
-    TRY(dalloc(c, &c->sigma, R));
+    TRY(dalloc(c, &c->sigma, R * R));
     const size_t qs = (size_t)row_stride(c->R, (int)c->fsz);
     TRY(dalloc_bytes(c, &c->rowI, (size_t)p.sI * qs * c->fsz));
     TRY(dalloc_bytes(c, &c->rowJ, (size_t)p.sJ * qs * c->fsz));
@@ -509,7 +514,7 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     HIPCHK(c, hipMemset(c->rowJ, 0, (size_t)p.sJ * qs * c->fsz));
     TRY(dalloc_bytes(c, &c->GmI, R * R * c->fsz));
     TRY(dalloc_bytes(c, &c->GmJ, R * R * c->fsz));
-    TRY(dalloc_bytes(c, &c->scaleJ, R * c->fsz));
+    TRY(dalloc_bytes(c, &c->scaleJ, R * R * c->fsz));
     TRY(dalloc(c, &c->part_row, (size_t)2 * c->nwg_row));
     TRY(dalloc(c, &c->part_col, (size_t)2 * c->nwg_col));
     TRY(dalloc(c, &c->st, 1));
@@ -668,7 +673,7 @@ int ircur_get_core(ircur_ctx* c, double* M_dev, double* W_dev, double* sigma_dev
     if (M_dev) HIPCHK(c, hipMemcpyAsync(M_dev, c->M, sizeof(double) * p.sI * p.sJ, hipMemcpyDeviceToDevice, c->stream));
     if (W_dev) HIPCHK(c, hipMemcpy2DAsync(W_dev, r * sizeof(double), c->W, R * sizeof(double), r * sizeof(double), p.sI, hipMemcpyDeviceToDevice, c->stream));
     if (V_dev) HIPCHK(c, hipMemcpy2DAsync(V_dev, r * sizeof(double), c->V, R * sizeof(double), r * sizeof(double), p.sJ, hipMemcpyDeviceToDevice, c->stream));
-    if (sigma_dev) HIPCHK(c, hipMemcpyAsync(sigma_dev, c->sigma, sizeof(double) * r, hipMemcpyDeviceToDevice, c->stream));
+    if (sigma_dev) HIPCHK(c, hipMemcpy2DAsync(sigma_dev, r * sizeof(double), c->sigma, R * sizeof(double), r * sizeof(double), r, hipMemcpyDeviceToDevice, c->stream));
     return IRCUR_OK;
 }
 

@@ -63,7 +63,7 @@ struct SideArgs {
     const void* P;         // B_k (side 0) or A_k^T (side 1): R x n, row stride n
     const void* rowdata;   // s x QS (QS = row_stride): [gathered factor | projection | Delta]
     const void* Gm;        // R x R: Gamma (side 0) or Gamma'^T (side 1)
-    const void* outscale;  // R scales of the output (nullptr: 1)
+    const void* outmat;    // R x R map applied to the output row (nullptr: identity)
     void* out;             // new factor, R x n, row stride n
     double* part;          // 2 doubles per workgroup: (residual, ||D_side||^2)
     int32_t nwg;
@@ -86,37 +86,46 @@ struct CoreArgs {
     const void* At;        // A_k^T, R x n1
     const void* B;         // B_k, R x n2
     double zeta; float zeta_f;
-    double* M;             // sI x sJ, double
+    double* M;             // sI x sJ, double, row-major
+    // The same matrix in two layouts for the SVD's matrix-core products, each
+    // made of 64-double blocks in lane order, zero outside sI x sJ:
+    //   MA block (ti, ks), ti < sI16/16, ks < sJ16/4:  lane l holds
+    //      M[16 ti + l%16][4 ks + l/16]            (A operand of M Q)
+    //   MB block (tj, ks), tj < sJ16/16, ks < sI16/4:  lane l holds
+    //      M[4 ks + l/16][16 tj + l%16]            (A operand of M^T Y)
+    double* MA;
+    double* MB;
     DevState* st;
 };
 
 struct SvdArgs {
-    const double* M;       // sI x sJ
-    int32_t sI, sJ, r, R, p;
+    const double* MA;      // M in the row-tiled layout (see CoreArgs)
+    const double* MB;      // M in the column-tiled layout
+    int32_t sI, sJ, r, R;
+    int32_t p;             // tile width P (16 or 32) >= R
     int32_t G;             // workgroups
-    int32_t bs;            // rows of M per workgroup
+    int32_t bs;            // rows of M per workgroup (multiple of 16)
     int32_t max_it;
     double tol;
-    int32_t warm;          // 0 random, 1 previous Ritz vectors, 2 B_k[:, J]^T
+    int32_t warm;          // 0 random, 1 previous right basis, 2 B_k[:, J]^T
     uint64_t salt;         // random fill salt
-    const double* prevV;   // sJ x p (warm == 1)
-    double* prevV_out;     // sJ x p
+    const double* prevV;   // sJ x R (warm == 1)
+    double* prevV_out;     // sJ x R
     const int32_t* I; const int32_t* J;
     int64_t n1, n2;
     const void* At;        // A_k^T (R x n1), factor dtype
     const void* B;         // B_k (R x n2), factor dtype
-    double* Zp;            // G x sJ x p scratch
-    double* Gp;            // G x p x p scratch
-    double* Tp;            // G x R x R scratch (Gamma partials)
-    double* W;             // sI x R out
-    double* V;             // sJ x R out
-    double* sigma;         // R out
+    double* Zp;            // G x sJ x P scratch
+    double* Gp;            // G x 2 x P x P scratch
+    double* W;             // sI x R out: orthonormal left basis Wt
+    double* V;             // sJ x R out: orthonormal right basis Q
+    double* sigma;         // R x R out: Kc with H_r(M) = Wt Kc Q^T
     void* rowI;            // sI x qs (factor dtype)
     void* rowJ;            // sJ x qs
     int32_t qs;            // row stride of rowI / rowJ (elements)
     void* GmI;             // R x R
     void* GmJ;             // R x R
-    void* scaleJ;          // R
+    void* scaleJ;          // R x R: Ly^-T, the column side's output map
     SvdInfo* info;         // one record (this iteration)
     DevState* st;
 };
@@ -139,6 +148,6 @@ hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
-size_t svd_lds_bytes(int sJ, int p, int bs, int R);
+size_t svd_lds_bytes(int sJ, int bs16, int P);
 
 }  // namespace ircur

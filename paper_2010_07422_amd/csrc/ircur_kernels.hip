@@ -18,7 +18,8 @@
 //              z = xr + Delta_a . B_k[:, j],  Delta = (I - W_r W_r^T) A_k[I, :],
 //              so z = R - W_r Gamma B_k[:, j] and
 //              ||R[:, j] - W_r B_{k+1}[:, j]||^2 = ||z||^2 - ||g_j||^2;
-//   column side is the same with (A_k^T, J, V_r, Gamma' = B_k[:, J] V_r).
+//   column side is the same with (A_k^T, J, Q, Gamma' = B_k[:, J] Q) and the
+//   output row mapped by Ly^-T (A_{k+1} = C Q Ly^-T).
 //   final: e_{k+1} and the device-side stop flag.
 //
 // Every element of a sampled row or column is computed as
@@ -118,7 +119,11 @@ __global__ __launch_bounds__(256) void core_kernel(CoreArgs a) {
     for (int c = 0; c < R; ++c) dot = fmaT(At[c * a.n1 + i], B[c * a.n2 + j], dot);
     bool o;
     const F v = entry_value<F>(d, dot, a.zeta, a.zeta_f, &o);
-    a.M[idx] = (double)v;
+    const double mv = (double)v;
+    a.M[idx] = mv;
+    const int sJ16 = ((a.sJ + 15) / 16) * 16, sI16 = ((a.sI + 15) / 16) * 16;
+    a.MA[((size_t)(ai >> 4) * (sJ16 >> 2) + (bj >> 2)) * 64 + ((bj & 3) << 4) + (ai & 15)] = mv;
+    a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
 }
 
 // ----------------------------------------------------------------- pass ---
@@ -246,9 +251,10 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     __syncthreads();
     if (wave == 0) {
         const F* __restrict__ Gm = (const F*)S.Gm;
-        const F* __restrict__ sc = (const F*)S.outscale;
+        const F* __restrict__ Tm = (const F*)S.outmat;
         F* __restrict__ out = (F*)S.out;
         double corr = 0.0;
+        F val[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const F g = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
@@ -256,8 +262,17 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
             F base = F(0);
 #pragma unroll
             for (int e = 0; e < R; ++e) base = fmaT(Gm[c * R + e], p[e], base);
-            const F val = base + g;
-            if (valid) out[c * n + col] = sc ? val * sc[c] : val;
+            val[c] = base + g;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            F o = val[c];
+            if (Tm) {
+                o = F(0);
+#pragma unroll
+                for (int d = 0; d < R; ++d) o = fmaT(val[d], Tm[d * R + c], o);
+            }
+            if (valid) out[c * n + col] = o;
         }
         double zl = ((redz[0][lane] + redz[1][lane]) + redz[2][lane]) + redz[3][lane];
         double dl = ((redd[0][lane] + redd[1][lane]) + redd[2][lane]) + redd[3][lane];

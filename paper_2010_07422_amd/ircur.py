@@ -236,18 +236,19 @@ class IRCUR:
         return I, J
 
     def core(self):
-        """(M, W_r, sigma_r, V_r) of the last iteration, float64 tensors."""
+        """(M, Wt, Kc, Q) of the last iteration, float64 tensors, with
+        H_r(M) = Wt @ Kc @ Q.T (Wt, Q orthonormal)."""
         import torch
         sI, sJ, r = self.p.sI, self.p.sJ, self.p.r
         dev = self.D.device
         M = torch.empty((sI, sJ), dtype=torch.float64, device=dev)
         W = torch.empty((sI, r), dtype=torch.float64, device=dev)
-        s = torch.empty((r,), dtype=torch.float64, device=dev)
+        K = torch.empty((r, r), dtype=torch.float64, device=dev)
         V = torch.empty((sJ, r), dtype=torch.float64, device=dev)
-        self._check(lib().ircur_get_core(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in (M, W, s, V))),
+        self._check(lib().ircur_get_core(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in (M, W, K, V))),
                     "ircur_get_core")
         self._sync_stream()
-        return M, W, s, V
+        return M, W, K, V
 
     def info(self):
         it = ctypes.c_int32()

@@ -39,11 +39,16 @@ def test_single_step_f64(n1, n2, r, s1, s2, k):
     if k > 0:
         ctx.set_factors(to_dev(torch, A.T, torch.float64), to_dev(torch, B, torch.float64), k)
     e = ctx.step(I, J)
-    M, W, s, V = ctx.core()
-    M = M.cpu().numpy(); s = s.cpu().numpy()
+    M, Wt, Kc, Q = (t.cpu().numpy() for t in ctx.core())
     # core: same entries, same masks away from the threshold
     assert np.max(np.abs(M - ref["M"])) <= 1e-12 * max(np.abs(ref["M"]).max(), 1e-300)
+    # top-r truncation: orthonormal bases, same singular values, same H_r(M)
+    assert np.allclose(Wt.T @ Wt, np.eye(r), atol=1e-12)
+    assert np.allclose(Q.T @ Q, np.eye(r), atol=1e-12)
+    s = np.linalg.svd(Kc, compute_uv=False)
     assert np.allclose(s, ref["sigma"], rtol=1e-11, atol=1e-12 * ref["sigma"][0])
+    Hr_ref = (ref["W_r"] * ref["sigma"]) @ ref["V_r"].T
+    assert np.linalg.norm(Wt @ Kc @ Q.T - Hr_ref) <= 1e-11 * np.linalg.norm(Hr_ref)
     A1, B1 = factors_np(ctx)
     assert O.factored_rel_diff(A1, B1, ref["A1"], ref["B1"]) <= 1e-11
     assert abs(e - ref["e"]) <= 1e-9 * max(ref["e"], 1e-300)
