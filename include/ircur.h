@@ -164,26 +164,38 @@ int ircur_get_core(ircur_ctx* ctx, double* M_dev, double* Wt_dev,
                    double* Kc_dev, double* Q_dev);
 
 /*
- * Output of Algorithm 1 for the last completed iteration k: C_k (n1 x sJ),
- * U_k^+ (sJ x sI) and R_k (sI x n2), and optionally the sparse
- * blocks S_I = [S_k]_{I,:} (sI x n2) and S_J = [S_k]_{:,J} (n1 x sJ), all in
- * the factor dtype (device).  Any pointer may be NULL.  Asynchronous.
+ * Output of Algorithm 1 (its C_k, U_k^+, R_k, eq. (2)-(3)) for the last
+ * completed iteration k, recomputed from that iteration's input factors
+ * (A_{k-1}, B_{k-1}), index sets (ircur_get_sets) and threshold zeta_k, with
+ * the same arithmetic the iteration used (so the blocks are bitwise those it
+ * used):  C_dev (n1 x sJ) = [D - S_k]_{:,J},  R_dev (sI x n2) = [D - S_k]_{I,:},
+ * Upinv_dev (sJ x sI) = U_k^+ = V_r Sigma_r^+ W_r^T (so L_k = C U^+ R), and the
+ * sparse blocks SI_dev = [S_k]_{I,:} (sI x n2), SJ_dev = [S_k]_{:,J} (n1 x sJ)
+ * of Phase I (eq. (4)).  All row-major, factor dtype, device; any pointer may
+ * be NULL.  Returns IRCUR_ERR_STATE if no iteration has completed since
+ * ircur_init, ircur_reset, ircur_set_factors or ircur_set_state.  Synchronises.
  */
 int ircur_get_cur(ircur_ctx* ctx, void* C_dev, void* Upinv_dev, void* R_dev,
                   void* SI_dev, void* SJ_dev);
 
 /*
- * Algorithm 2 (CUR to SVD) applied to the current estimate L_k = A_k B_k:
- * W_dev (n1 x r), sigma_dev (r), V_dev (n2 x r), all double, with
- * L_k = W diag(sigma) V^T.  Asynchronous.
+ * Algorithm 2 (CUR to SVD) applied to the current estimate in factored form,
+ * L_k = A_k I_r B_k: QR of A_k and of B_k^T (Cholesky QR, twice, in FP64),
+ * SVD of the r x r product of the triangular factors (one-sided Jacobi),
+ * then W = Q_A U_M, V = Q_B V_M.  Outputs (device, double, row-major):
+ * W_dev (n1 x r), sigma_dev (r, descending), V_dev (n2 x r), with
+ * L_k = W diag(sigma) V^T; columns beyond the numerical rank of L_k are zero.
+ * Any pointer may be NULL.  Synchronises.
  */
 int ircur_to_svd(ircur_ctx* ctx, double* W_dev, double* sigma_dev, double* V_dev);
 
 /*
- * Full sparse part S = T_zeta(D - A_k B_k) over all of D (the video
- * foreground), written to S_dev (n1 x n2, row stride ldS, dtype of D), with
- * zeta <= 0 meaning the threshold of the last completed iteration.
- * Returns the number of nonzeros in *nnz_out (may be NULL; synchronises if not).
+ * Full sparse part S = T_zeta(D - A_k B_k) over all of D (the hard threshold
+ * of eq. (4) applied to every entry; the foreground of the video application
+ * of section 5), written to S_dev (n1 x n2, row stride ldS >= n2, dtype of D,
+ * device).  zeta < 0 selects zeta_{k+1} = gamma^k zeta_0, the threshold the
+ * next iteration would apply to D - L_k; zeta >= 0 is used as given.  The
+ * number of nonzeros goes to *nnz_out (may be NULL; synchronises if not).
  */
 int ircur_sparse_full(ircur_ctx* ctx, double zeta, void* S_dev, int64_t ldS,
                       int64_t* nnz_out);

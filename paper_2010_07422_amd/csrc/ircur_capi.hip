@@ -117,6 +117,11 @@ struct ircur_ctx {
     void* GmI = nullptr;
     void* GmJ = nullptr;
     void* scaleJ = nullptr;
+    double* TAd = nullptr;
+    int32_t* Icur = nullptr;        // index sets of an export (device)
+    int32_t* Jcur = nullptr;
+    unsigned long long* nnz = nullptr;
+    double* alg2_buf = nullptr;     // Algorithm 2 workspace (allocated on first use)
     double* part_row = nullptr;
     double* part_col = nullptr;
     int nwg_row = 0, nwg_col = 0;
@@ -126,6 +131,7 @@ struct ircur_ctx {
     double* hist = nullptr;        // max_iter
     int32_t k = 0;                 // completed iterations (host view after sync)
     int32_t k_enq = 0;             // next iteration to enqueue
+    int32_t k_base = 0;            // k at which the factors were last set from outside
     int32_t batch = 0;             // batches enqueued (selects the ring half)
     bool stopped = false;
     hipEvent_t h2d[2] = {nullptr, nullptr};
@@ -148,6 +154,12 @@ int fail(ircur_ctx* c, int code, const char* msg) {
     if (c) c->err = msg;
     return code;
 }
+
+#define TRY_ALLOC(ctx, x)            \
+    do {                             \
+        int r_ = (x);                \
+        if (r_) return r_;           \
+    } while (0)
 
 #define HIPCHK(ctx, x)                                                        \
     do {                                                                      \
@@ -205,7 +217,7 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
-                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->part_row, c->part_col, c->st,
+                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->st,
                     c->info, c->hist};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -234,6 +246,7 @@ int reset_state(ircur_ctx* c) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->k = 0;
     c->k_enq = 0;
+    c->k_base = 0;
     c->acc_next = 0;
     c->stopped = false;
     c->have_prevV = false;
@@ -313,6 +326,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.Zp = c->Zp; sa.Gp = c->Gp;
     sa.W = c->W; sa.V = c->V; sa.sigma = c->sigma;
     sa.rowI = c->rowI; sa.rowJ = c->rowJ; sa.GmI = c->GmI; sa.GmJ = c->GmJ; sa.scaleJ = c->scaleJ;
+    sa.TAd = c->TAd;
     sa.qs = row_stride(c->R, (int)c->fsz);
     sa.info = c->info + k; sa.st = c->st;
     HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
@@ -515,6 +529,10 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     TRY(dalloc_bytes(c, &c->GmI, R * R * c->fsz));
     TRY(dalloc_bytes(c, &c->GmJ, R * R * c->fsz));
     TRY(dalloc_bytes(c, &c->scaleJ, R * R * c->fsz));
+    TRY(dalloc(c, &c->TAd, R * R));
+    TRY(dalloc(c, &c->Icur, (size_t)p.sI));
+    TRY(dalloc(c, &c->Jcur, (size_t)p.sJ));
+    TRY(dalloc(c, &c->nnz, 1));
     TRY(dalloc(c, &c->part_row, (size_t)2 * c->nwg_row));
     TRY(dalloc(c, &c->part_col, (size_t)2 * c->nwg_col));
     TRY(dalloc(c, &c->st, 1));
@@ -636,6 +654,7 @@ int ircur_set_factors(ircur_ctx* c, const void* At_dev, const void* B_dev, int32
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->k = k;
     c->k_enq = k;
+    c->k_base = k;
     c->acc_next = k;
     c->stopped = false;
     c->have_prevV = false;
@@ -674,6 +693,83 @@ int ircur_get_core(ircur_ctx* c, double* M_dev, double* W_dev, double* sigma_dev
     if (W_dev) HIPCHK(c, hipMemcpy2DAsync(W_dev, r * sizeof(double), c->W, R * sizeof(double), r * sizeof(double), p.sI, hipMemcpyDeviceToDevice, c->stream));
     if (V_dev) HIPCHK(c, hipMemcpy2DAsync(V_dev, r * sizeof(double), c->V, R * sizeof(double), r * sizeof(double), p.sJ, hipMemcpyDeviceToDevice, c->stream));
     if (sigma_dev) HIPCHK(c, hipMemcpy2DAsync(sigma_dev, r * sizeof(double), c->sigma, R * sizeof(double), r * sizeof(double), r, hipMemcpyDeviceToDevice, c->stream));
+    return IRCUR_OK;
+}
+
+int ircur_get_cur(ircur_ctx* c, void* C_dev, void* Upinv_dev, void* R_dev, void* SI_dev, void* SJ_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (c->k <= c->k_base) return fail(c, IRCUR_ERR_STATE, "no iteration completed since the factors were set");
+    const ircur_params& p = c->p;
+    const int it = c->k - 1;                 // 0-based index of the last completed iteration
+    const int prev = it & 1;                 // its input factors
+    HIPCHK(c, hipMemcpyAsync(c->Icur, c->setsI.data() + (size_t)it * p.sI, sizeof(int32_t) * p.sI,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->Jcur, c->setsJ.data() + (size_t)it * p.sJ, sizeof(int32_t) * p.sJ,
+                             hipMemcpyHostToDevice, c->stream));
+    CurArgs a{};
+    a.D = c->D; a.ldD = p.ldD; a.Dt = c->Dt; a.ldDt = c->ldDt;
+    a.I = c->Icur; a.J = c->Jcur; a.sI = p.sI; a.sJ = p.sJ; a.n1 = p.n1; a.n2 = p.n2;
+    a.At = c->At[prev]; a.B = c->B[prev];
+    a.zeta = zeta_at(p, it); a.zeta_f = round_down_float(a.zeta);
+    a.Rout = R_dev; a.SI = SI_dev; a.Cout = C_dev; a.SJ = SJ_dev;
+    if (R_dev || SI_dev || C_dev || SJ_dev) HIPCHK(c, launch_cur(a, p.dtype, c->R, c->stream));
+    if (Upinv_dev)
+        HIPCHK(c, launch_upinv(c->V, c->TAd, c->W, p.sI, p.sJ, c->R, Upinv_dev, p.dtype == IRCUR_F64 ? 0 : 1,
+                               c->stream));
+    // the pageable index copies above must not outlive this call's host data
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IRCUR_OK;
+}
+
+int ircur_to_svd(ircur_ctx* c, double* W_dev, double* sigma_dev, double* V_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const ircur_params& p = c->p;
+    const int nwg = (int)std::min<int64_t>(256, (std::max(p.n1, p.n2) + 127) / 128);
+    const size_t R = c->R;
+    if (!c->alg2_buf) {
+        // parts (2 x 256 x R x R), T1 and Tf (2 x R x R each)
+        TRY_ALLOC(c, dalloc(c, &c->alg2_buf, 2 * 256 * R * R + 4 * R * R));
+    }
+    Alg2Args a{};
+    const int cur = c->k & 1;
+    a.X[0] = c->At[cur]; a.X[1] = c->B[cur];
+    a.n[0] = p.n1; a.n[1] = p.n2;
+    a.r = p.r; a.R = c->R; a.fdt = p.dtype == IRCUR_F64 ? 0 : 1; a.nwg = nwg;
+    a.parts = c->alg2_buf;
+    a.T1 = c->alg2_buf + 2 * 256 * R * R;
+    a.Tf = a.T1 + 2 * R * R;
+    a.sigma_out = sigma_dev;
+    a.out[0] = W_dev; a.out[1] = V_dev;
+    HIPCHK(c, launch_alg2(a, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IRCUR_OK;
+}
+
+int ircur_sparse_full(ircur_ctx* c, double zeta, void* S_dev, int64_t ldS, int64_t* nnz_out) {
+    if (!c || !S_dev || ldS < c->p.n2 || std::isnan(zeta)) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const ircur_params& p = c->p;
+    const int cur = c->k & 1;
+    SparseArgs a{};
+    a.D = c->D; a.ldD = p.ldD; a.n1 = p.n1; a.n2 = p.n2;
+    a.At = c->At[cur]; a.B = c->B[cur];
+    a.zeta = zeta < 0.0 ? zeta_at(p, c->k) : zeta;
+    a.zeta_f = round_down_float(a.zeta);
+    a.S = S_dev; a.ldS = ldS;
+    a.nnz = nnz_out ? c->nnz : nullptr;
+    if (nnz_out) HIPCHK(c, hipMemsetAsync(c->nnz, 0, sizeof(unsigned long long), c->stream));
+    HIPCHK(c, launch_sparse_full(a, p.dtype, c->R, c->stream));
+    if (nnz_out) {
+        unsigned long long h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, c->nnz, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *nnz_out = (int64_t)h;
+    }
     return IRCUR_OK;
 }
 
@@ -761,6 +857,7 @@ int ircur_set_state(ircur_ctx* c, const void* buf, size_t bytes) {
     HIPCHK(c, hipMemcpy(c->st, &h, sizeof(DevState), hipMemcpyHostToDevice));
     c->k = k;
     c->k_enq = k;
+    c->k_base = k;
     c->acc_next = k;
     c->stopped = hdr[2] != 0;
     c->have_prevV = false;

@@ -126,6 +126,7 @@ struct SvdArgs {
     void* GmI;             // R x R
     void* GmJ;             // R x R
     void* scaleJ;          // R x R: Ly^-T, the column side's output map
+    double* TAd;           // R x R: Ly^-T in double (for U^+ on export)
     SvdInfo* info;         // one record (this iteration)
     DevState* st;
 };
@@ -140,6 +141,46 @@ struct FinArgs {
     DevState* st;
 };
 
+// Export of the last completed iteration (C, R, S blocks), factor dtype out.
+struct CurArgs {
+    const void* D; int64_t ldD;
+    const void* Dt; int64_t ldDt;
+    const int32_t* I; const int32_t* J;
+    int32_t sI, sJ;
+    int64_t n1, n2;
+    const void* At;        // A_{k-1}^T (input factors of that iteration)
+    const void* B;         // B_{k-1}
+    double zeta; float zeta_f;
+    void* Rout;            // sI x n2 or nullptr
+    void* SI;              // sI x n2 or nullptr
+    void* Cout;            // n1 x sJ or nullptr
+    void* SJ;              // n1 x sJ or nullptr
+};
+
+// Full sparse part T_zeta(D - A B), written in the dtype of D.
+struct SparseArgs {
+    const void* D; int64_t ldD;
+    int64_t n1, n2;
+    const void* At; const void* B;
+    double zeta; float zeta_f;
+    void* S; int64_t ldS;
+    unsigned long long* nnz;   // accumulated count (nullptr: not counted)
+};
+
+// Algorithm 2 on the factored estimate (FP64).
+struct Alg2Args {
+    const void* X[2];      // A^T (R x n1), B (R x n2), factor dtype
+    int64_t n[2];
+    int32_t r, R;
+    int32_t fdt;           // 0: double factors, 1: float factors
+    int32_t nwg;           // gram workgroups per side
+    double* parts;         // 2 x nwg x R x R
+    double* T1;            // 2 x R x R: first-pass maps L1^-T
+    double* Tf;            // 2 x R x R: output maps
+    double* sigma_out;     // r, or nullptr
+    double* out[2];        // W (n1 x r), V (n2 x r), or nullptr
+};
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_transpose(const void* src, int64_t lds, void* dst, int64_t ldd,
                             int64_t rows, int64_t cols, int elem_bytes, hipStream_t s);
@@ -149,5 +190,10 @@ hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
 size_t svd_lds_bytes(int sJ, int bs16, int P);
+hipError_t launch_cur(const CurArgs& a, int dtype, int R, hipStream_t s);
+hipError_t launch_upinv(const double* V, const double* TA, const double* W, int sI, int sJ, int R,
+                        void* out, int dtype, hipStream_t s);
+hipError_t launch_sparse_full(const SparseArgs& a, int dtype, int R, hipStream_t s);
+hipError_t launch_alg2(const Alg2Args& a, hipStream_t s);
 
 }  // namespace ircur

@@ -27,46 +27,13 @@
 //     v = |x| > zeta ? d - x : d  (entry of D - S_{k+1})
 // with the same chain in the core kernel and in both sides of the pass, so
 // the I x J block is bit-identical wherever it is computed.
-#include "ircur_internal.h"
+#include "ircur_device.h"
 
 #include <stdint.h>
 
 #include <algorithm>
 
 namespace ircur {
-
-// ---------------------------------------------------------------- types ---
-
-struct bf16_t { uint16_t bits; };
-
-template <typename T, typename F> __device__ __forceinline__ F ld(const T* p);
-template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return *p; }
-template <> __device__ __forceinline__ float ld<float, float>(const float* p) { return *p; }
-template <> __device__ __forceinline__ float ld<bf16_t, float>(const bf16_t* p) {
-    return __uint_as_float(((uint32_t)p->bits) << 16);
-}
-
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// |x| > zeta evaluated exactly: in float, against the largest float <= zeta.
-__device__ __forceinline__ bool above(double ax, double z, float) { return ax > z; }
-__device__ __forceinline__ bool above(float ax, double, float zf) { return ax > zf; }
-
-template <typename F>
-__device__ __forceinline__ F entry_value(F d, F dot, double zeta, float zeta_f, bool* is_out) {
-    const F x = d - dot;
-    const bool o = above(x < F(0) ? -x : x, zeta, zeta_f);
-    *is_out = o;
-    return o ? d - x : d;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    // Fixed butterfly over the 64 lanes: every lane ends with the same sum,
-    // formed in the same order on every run.
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // ------------------------------------------------------------ transpose ---
 
@@ -379,24 +346,6 @@ static hipError_t pass_r(const PassArgs& a0, hipStream_t s) {
     else pass_kernel<T, F, R, false><<<grid, 256, lds, s>>>(a);
     return hipGetLastError();
 }
-
-#define IRCUR_RANK_SWITCH(FN, T, F, R, ...)                     \
-    switch (R) {                                                \
-        case 1: return FN<T, F, 1>(__VA_ARGS__);                \
-        case 2: return FN<T, F, 2>(__VA_ARGS__);                \
-        case 3: return FN<T, F, 3>(__VA_ARGS__);                \
-        case 4: return FN<T, F, 4>(__VA_ARGS__);                \
-        case 5: return FN<T, F, 5>(__VA_ARGS__);                \
-        case 6: return FN<T, F, 6>(__VA_ARGS__);                \
-        case 8: return FN<T, F, 8>(__VA_ARGS__);                \
-        case 10: return FN<T, F, 10>(__VA_ARGS__);              \
-        case 12: return FN<T, F, 12>(__VA_ARGS__);              \
-        case 16: return FN<T, F, 16>(__VA_ARGS__);              \
-        case 20: return FN<T, F, 20>(__VA_ARGS__);              \
-        case 24: return FN<T, F, 24>(__VA_ARGS__);              \
-        case 32: return FN<T, F, 32>(__VA_ARGS__);              \
-        default: return hipErrorInvalidValue;                   \
-    }
 
 hipError_t launch_core(const CoreArgs& a, int dtype, int R, hipStream_t s) {
     if (dtype == 0) { IRCUR_RANK_SWITCH(core_r, double, double, R, a, s) }

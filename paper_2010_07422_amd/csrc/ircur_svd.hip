@@ -634,6 +634,7 @@ __global__ __launch_bounds__(256) void svd_sub_kernel(SvdArgs a) {
             fput(a.GmI, e, Gam[c * P + d], fd);           // Gamma[c][d]
             fput(a.GmJ, e, Gam2[d * P + c], fd);          // Gamma'[d][c]
             fput(a.scaleJ, e, TA[c * P + d], fd);         // Ly^-T
+            a.TAd[e] = TA[c * P + d];
             a.sigma[e] = Ls[d * P + c];                   // Kc = Ly^T: H_r(M) = Wt Kc Q^T
         }
         if (tid == 0) {

@@ -250,6 +250,50 @@ class IRCUR:
         self._sync_stream()
         return M, W, K, V
 
+    def cur(self):
+        """Output of Algorithm 1 for the last completed iteration: dict with
+        C (n1 x sJ), Upinv (sJ x sI), R (sI x n2), S_I (sI x n2), S_J (n1 x sJ),
+        in the factor dtype, plus the index sets I, J."""
+        import torch
+        n1, n2, sI, sJ = self.p.n1, self.p.n2, self.p.sI, self.p.sJ
+        dev = self.D.device
+        out = {"C": torch.empty((n1, sJ), dtype=self.fdtype, device=dev),
+               "Upinv": torch.empty((sJ, sI), dtype=self.fdtype, device=dev),
+               "R": torch.empty((sI, n2), dtype=self.fdtype, device=dev),
+               "S_I": torch.empty((sI, n2), dtype=self.fdtype, device=dev),
+               "S_J": torch.empty((n1, sJ), dtype=self.fdtype, device=dev)}
+        self._check(lib().ircur_get_cur(self.h, *(ctypes.c_void_p(out[k].data_ptr())
+                                                  for k in ("C", "Upinv", "R", "S_I", "S_J"))),
+                    "ircur_get_cur")
+        out["I"], out["J"] = self.sets()
+        return out
+
+    def to_svd(self):
+        """Algorithm 2 on the current factors: (W n1 x r, sigma r, V n2 x r),
+        float64, L_k = W diag(sigma) V^T."""
+        import torch
+        n1, n2, r = self.p.n1, self.p.n2, self.p.r
+        dev = self.D.device
+        W = torch.empty((n1, r), dtype=torch.float64, device=dev)
+        sig = torch.empty((r,), dtype=torch.float64, device=dev)
+        V = torch.empty((n2, r), dtype=torch.float64, device=dev)
+        self._check(lib().ircur_to_svd(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in (W, sig, V))),
+                    "ircur_to_svd")
+        return W, sig, V
+
+    def sparse_full(self, zeta=-1.0, out=None):
+        """T_zeta(D - A_k B_k) over all of D in the dtype of D; zeta < 0 picks
+        gamma^k zeta_0.  Returns (S, nnz)."""
+        import torch
+        n1, n2 = self.p.n1, self.p.n2
+        S = torch.empty((n1, n2), dtype=self.D.dtype, device=self.D.device) if out is None else out
+        if S.dim() != 2 or S.shape != (n1, n2) or S.stride(1) != 1 or S.dtype != self.D.dtype:
+            raise ValueError("out must be an n1 x n2 tensor of D's dtype with unit column stride")
+        nnz = ctypes.c_int64()
+        self._check(lib().ircur_sparse_full(self.h, float(zeta), ctypes.c_void_p(S.data_ptr()), S.stride(0),
+                                            ctypes.byref(nnz)), "ircur_sparse_full")
+        return S, nnz.value
+
     def info(self):
         it = ctypes.c_int32()
         res = ctypes.c_double()
