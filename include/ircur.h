@@ -192,7 +192,7 @@ int ircur_to_svd(ircur_ctx* ctx, double* W_dev, double* sigma_dev, double* V_dev
 /*
  * Full sparse part S = T_zeta(D - A_k B_k) over all of D (the hard threshold
  * of eq. (4) applied to every entry; the foreground of the video application
- * of section 5), written to S_dev (n1 x n2, row stride ldS >= n2, dtype of D,
+ * of section 4.2), written to S_dev (n1 x n2, row stride ldS >= n2, dtype of D,
  * device).  zeta < 0 selects zeta_{k+1} = gamma^k zeta_0, the threshold the
  * next iteration would apply to D - L_k; zeta >= 0 is used as given.  The
  * number of nonzeros goes to *nnz_out (may be NULL; synchronises if not).

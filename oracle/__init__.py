@@ -17,4 +17,4 @@ unrolled  The unrolled K-step IRCUR with a gated threshold and its hand-derived
           reverse-mode adjoint.  The paper does not define this variant; its
           readings are stated in the module.
 """
-from . import sampler, ircur  # noqa: F401
+from . import sampler, ircur, unrolled  # noqa: F401

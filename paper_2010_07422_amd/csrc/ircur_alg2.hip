@@ -1,4 +1,4 @@
-// Algorithm 2 (CUR to SVD, section 3.5) on the device, in FP64, for the
+// Algorithm 2 (CUR to SVD, section 3.3) on the device, in FP64, for the
 // factored estimate L = A I_r B (A = A_k, n1 x r; B = B_k, r x n2):
 //
 //   QR of A and of B^T:  Cholesky QR applied twice (the second pass corrects

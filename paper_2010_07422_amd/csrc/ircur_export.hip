@@ -5,7 +5,7 @@
 //           (section 3.1), recomputed for the last completed iteration from
 //           its input factors, index sets and threshold;
 //   sparse  the full sparse part T_zeta(D - A_k B_k) over all of D (the
-//           foreground of the video application, section 5).
+//           foreground of the video application, section 4.2).
 //
 // Every entry uses the same fma chain and threshold test as the iteration's
 // core and pass kernels, so the exported blocks equal, bit for bit, the
