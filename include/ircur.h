@@ -244,6 +244,77 @@ void        ircur_destroy(ircur_ctx* ctx);
 const char* ircur_strerror(int status);
 const char* ircur_last_error(const ircur_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Unrolled, differentiable mode.
+ *
+ * The paper's iteration uses the hard threshold of eq. (4) with the schedule
+ * zeta_{k+1} = gamma^k zeta_0 (Algorithm 1).  This mode runs K iterations of
+ * Algorithm 1 (resampled index sets, IRCUR-R) on a batch of independent
+ * instances with one threshold zeta_k per iteration, shared by the batch,
+ * and the gated sparse part S = x g, g = sigmoid((|x| - zeta_k) / (tau_rel
+ * zeta_k)) in place of T_zeta (tau_rel = 0 is eq. (4) exactly).  Per instance
+ *     loss_b = ||A_K B_K - W* V*^T||_F / ||W* V*^T||_F
+ * against a target L* = W* V*^T.  ircur_backward returns d(sum_b w_b loss_b)
+ * / d zeta_k through the factor products, the gate and the rank-r
+ * pseudo-inverse of the core (first-order perturbation of the truncated SVD,
+ * which needs sigma_r > sigma_{r+1}); the gathered rows and columns of D are
+ * recomputed, not stored.
+ * ---------------------------------------------------------------------- */
+typedef struct ircur_unrolled ircur_unrolled;
+
+typedef struct {
+    int64_t n1, n2, ldD;   /* D: n1 x n2, row stride ldD >= n2                   */
+    int32_t sI, sJ;        /* |I|, |J|: r <= sI <= min(n1, 176), r <= sJ <= min(n2, 176) */
+    const void* D;         /* device, dtype of the batch; borrowed                 */
+    const void* Dt;        /* optional device D^T (n2 x n1, row stride ldDt), or NULL */
+    int64_t ldDt;
+    const void* Wstar;     /* device, n1 x r, row-major, factor dtype: target W*   */
+    const void* Vstar;     /* device, n2 x r: target V* (L* = W* V*^T)             */
+    uint64_t seed;         /* sampler seed; step k uses stream k (see ircur_sample) */
+} ircur_instance;
+
+/*
+ * Create a batch: nb instances, rank r (1..16), K steps, dtype IRCUR_F64 or
+ * IRCUR_F32 (factors in the same type, the core SVD and its adjoint in
+ * double), gate width tau_rel >= 0.  Draws and uploads every index set,
+ * builds D^T where not given and allocates the tape.  Synchronises.
+ * Errors: IRCUR_ERR_ARG, IRCUR_ERR_UNSUPPORTED (sizes beyond the limits
+ * above), IRCUR_ERR_ALLOC, IRCUR_ERR_DEVICE.  On error *out is NULL.
+ */
+int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int32_t nb,
+                          int32_t r, int32_t K, int32_t dtype, double tau_rel, void* stream);
+
+/*
+ * Forward pass from L_0 = 0 with thresholds zeta_dev[0..K-1] (device,
+ * double; an FP32 parameter converts exactly).  Writes loss_b to loss_dev[b]
+ * (device, nb doubles; may be NULL).  Asynchronous.
+ */
+int ircur_unrolled_forward(ircur_unrolled* u, const double* zeta_dev, double* loss_dev);
+
+/*
+ * Reverse sweep of the last forward pass: dzeta_dev[k] (device, K doubles)
+ * = sum_b w_b d loss_b / d zeta_k with w = dloss_dev (device, nb doubles; NULL
+ * means all ones).  Asynchronous.  IRCUR_ERR_STATE without a forward pass.
+ */
+int ircur_backward(ircur_unrolled* u, const double* dloss_dev, double* dzeta_dev);
+
+/* Factors of instance b after step k (0..K): A_k^T (r x n1), B_k (r x n2). */
+int ircur_unrolled_get_factors(ircur_unrolled* u, int32_t b, int32_t k, void* At_dev, void* B_dev);
+
+/* Index sets of instance b at step k (host, sorted). */
+int ircur_unrolled_get_sets(ircur_unrolled* u, int32_t b, int32_t k, int32_t* I_host, int32_t* J_host);
+
+/*
+ * Per-instance flags of the last passes (host, nb values): 1 a resolvent
+ * solve of the backward stopped at its cap, 2 sigma_r ~ 0 in some core,
+ * 4 an SVD hit its iteration cap, 8 the pinv rule dropped a component,
+ * 16 SVD failure.  Synchronises.  Returns IRCUR_ERR_SVD if any has 16.
+ */
+int ircur_unrolled_status(ircur_unrolled* u, int32_t* flags_host);
+
+void        ircur_unrolled_destroy(ircur_unrolled* u);
+const char* ircur_unrolled_last_error(const ircur_unrolled* u);
+
 #ifdef __cplusplus
 }
 #endif

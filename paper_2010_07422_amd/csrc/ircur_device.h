@@ -5,11 +5,15 @@
 
 #include "ircur_internal.h"
 
+#include <algorithm>
+
 namespace ircur {
 
 // ---------------------------------------------------------------- types ---
 
 struct bf16_t { uint16_t bits; };
+// 16-byte vector (a native vector type, so arrays of it stay in registers)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T, typename F> __device__ __forceinline__ F ld(const T* p);
 template <> __device__ __forceinline__ double ld<double, double>(const double* p) { return *p; }
@@ -54,6 +58,177 @@ template <typename T> __device__ __forceinline__ T from_f(double v);
 template <> __device__ __forceinline__ double from_f<double>(double v) { return v; }
 template <> __device__ __forceinline__ float from_f<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ bf16_t from_f<bf16_t>(double v) { return to_bf16((float)v); }
+
+// Gate of the unrolled mode: g = sigmoid((|x| - zeta) / tauz), tauz = tau_rel zeta
+// (tends to the hard threshold of eq. (4) as tau_rel -> 0).
+__device__ __forceinline__ double exp_t(double v) { return exp(v); }
+__device__ __forceinline__ float exp_t(float v) { return expf(v); }
+template <typename F>
+__device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
+    const F ax = x < F(0) ? -x : x;
+    return F(1) / (F(1) + exp_t(-(ax - zeta) / tauz));
+}
+
+// One workgroup: 64 consecutive outputs (one per lane) x all s gathered rows.
+// Wave w takes a contiguous quarter of the rows and keeps U row loads of D in
+// flight (the next group is issued before the current one is consumed); the
+// four partial sums are reduced in LDS at the end.  The per-row data
+// (gathered factor row, projection row, Delta row; QS elements per row, 16-byte
+// aligned) is wave-uniform: the workgroup stages it in LDS with batched
+// 16-byte loads (all rows at once unless they exceed the LDS budget) and reads
+// it back as broadcast loads.  The index arrays carry kIndexPad valid trailing
+// entries, so a group may read past the end of a wave's rows.
+template <typename T> struct RowsInFlight { static constexpr int value = 8; };
+template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
+template <> struct RowsInFlight<double> { static constexpr int value = 4; };
+
+template <typename T, typename F, int R, bool LIT, bool GATE = false>
+__device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta, float zeta_f,
+                                          F (*red)[R][64], double (*redz)[64], double (*redd)[64],
+                                          F* qstage, int segmax, F tauz = F(0)) {
+    constexpr int U = RowsInFlight<T>::value;
+    constexpr int QS = RowStride<F, R>::value;
+    constexpr int UPR = QS * (int)sizeof(F) / 16;          // 16-byte units per row
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t col = (int64_t)wg * 64 + lane;
+    const bool valid = col < S.n;
+    const int64_t n = S.n;
+    const T* __restrict__ X = (const T*)S.X;
+    const F* __restrict__ P = (const F*)S.P;
+    const u32x4* __restrict__ rd4 = (const u32x4*)S.rowdata;
+    const int32_t* __restrict__ rows = S.rows;
+    const int64_t ldX = S.ldX;
+
+    F p[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) p[c] = valid ? P[c * n + col] : F(0);
+    F acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = F(0);
+    F zz = F(0), dd = F(0);
+    const T* __restrict__ Xc = X + (valid ? col : 0);   // invalid lanes read column 0
+    const int chunk = (S.s + 3) >> 2;
+    const int a_begin = wave * chunk;
+    const int a_end = min(S.s, a_begin + chunk);
+    // rows per stage: whole chunk if it fits, else segmax (a multiple of U)
+    const int SEG = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    F* __restrict__ qw = qstage + wave * (SEG * QS);
+
+    F dv[U];
+    if (a_end > a_begin) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) dv[u] = ld<T, F>(Xc + (int64_t)rows[a_begin + u] * ldX);
+    }
+    for (int seg0 = 0; seg0 < chunk; seg0 += SEG) {       // uniform over the workgroup
+        const int sb = a_begin + seg0;
+        const int se = min(a_end, sb + SEG);
+        __syncthreads();                                  // previous segment consumed
+        {
+            const int units = 4 * SEG * UPR;
+            for (int base = threadIdx.x; base < units; base += 256 * 8) {
+                u32x4 v[8];
+                int dst[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int un = base + u * 256;
+                    int64_t src = 0;
+                    bool ok = false;
+                    if (un < units) {
+                        const int w = un / (SEG * UPR);
+                        const int rem = un - w * (SEG * UPR);
+                        const int rr = rem / UPR, kk = rem - rr * UPR;
+                        const int row = w * chunk + seg0 + rr;
+                        ok = seg0 + rr < chunk && row < S.s;
+                        src = (int64_t)row * UPR + kk;
+                    }
+                    dst[u] = ok ? un : -1;
+                    v[u] = rd4[ok ? src : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dst[u] >= 0) ((u32x4*)qstage)[dst[u]] = v[u];
+            }
+        }
+        __syncthreads();
+        for (int a0 = sb; a0 < se; a0 += U) {
+            F cur[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = dv[u];
+            if (a0 + U < a_end) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) dv[u] = ld<T, F>(Xc + (int64_t)rows[a0 + U + u] * ldX);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int a = a0 + u;
+                if (a < se) {
+                    const F d = valid ? cur[u] : F(0);
+                    const F* q = qw + (a - sb) * QS;
+                    F dot = F(0);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c], dot);
+                    const F x = d - dot;
+                    F xr;
+                    if (GATE) xr = x - x * gate_value<F>(x, (F)zeta, tauz);
+                    else xr = above(x < F(0) ? -x : x, zeta, zeta_f) ? F(0) : x;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] = fmaT(q[R + c], xr, acc[c]);
+                    if (LIT) {
+                        F z = xr;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) z = fmaT(q[2 * R + c], p[c], z);
+                        zz = fmaT(z, z, zz);
+                    } else {
+                        zz = fmaT(xr, xr, zz);
+                    }
+                    dd = fmaT(d, d, dd);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int c = 0; c < R; ++c) red[wave][c][lane] = acc[c];
+    redz[wave][lane] = (double)zz;
+    redd[wave][lane] = (double)dd;
+    __syncthreads();
+    if (wave == 0) {
+        const F* __restrict__ Gm = (const F*)S.Gm;
+        const F* __restrict__ Tm = (const F*)S.outmat;
+        F* __restrict__ out = (F*)S.out;
+        double corr = 0.0;
+        F val[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const F g = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+            if (LIT) corr = __builtin_fma((double)g, (double)g, corr);
+            F base = F(0);
+#pragma unroll
+            for (int e = 0; e < R; ++e) base = fmaT(Gm[c * R + e], p[e], base);
+            val[c] = base + g;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            F o = val[c];
+            if (Tm) {
+                o = F(0);
+#pragma unroll
+                for (int d = 0; d < R; ++d) o = fmaT(val[d], Tm[d * R + c], o);
+            }
+            if (valid) out[c * n + col] = o;
+        }
+        double zl = ((redz[0][lane] + redz[1][lane]) + redz[2][lane]) + redz[3][lane];
+        double dl = ((redd[0][lane] + redd[1][lane]) + redd[2][lane]) + redd[3][lane];
+        if (!valid) { zl = 0.0; dl = 0.0; corr = 0.0; }
+        const double res = wave_sum(zl - corr);
+        const double dsum = wave_sum(dl);
+        if (lane == 0) {
+            S.part[2 * wg] = res;
+            S.part[2 * wg + 1] = dsum;
+        }
+    }
+}
 
 #define IRCUR_RANK_SWITCH(FN, T, F, R, ...)                     \
     switch (R) {                                                \

@@ -181,11 +181,61 @@ struct Alg2Args {
     double* out[2];        // W (n1 x r), V (n2 x r), or nullptr
 };
 
+// ---- unrolled mode (a batch of independent instances) --------------------
+// Grouped launches map blockIdx.x to (instance b, local block) through an
+// offset table off[0..nb] (off[b] = first block of instance b).
+
+// Loss of one instance: Grams of [A_K | W*] (n1 rows) and [B_K^T | V*] (n2 rows).
+struct ULoss {
+    const void* At; const void* B;        // A_K^T (R x n1), B_K (R x n2), factor dtype
+    const void* Ws; const void* Vs;       // W* (n1 x r), V* (n2 x r), factor dtype
+    int64_t n1, n2;
+    int32_t r, R;
+    int32_t nwgA, nwgB;                   // gram blocks per side
+    double* gpart;                        // (nwgA + nwgB) x (2R)^2 partials
+    double* gsum;                         // 2 x (2R)^2 reduced Grams
+    double* loss;                         // 1 value
+    void* Abar; void* Bbar;               // loss adjoints out (R x n1, R x n2)
+};
+
+// Reverse sweep of one step of one instance.
+struct UBack {
+    const void* D; int64_t ldD;
+    const void* Dt; int64_t ldDt;
+    int64_t n1, n2;
+    int32_t sI, sJ, r, R;
+    const int32_t* I; const int32_t* J;   // this step's sets
+    const int32_t* posJ;                  // n2: index of column j in J, or -1
+    const void* At; const void* B;        // A_k^T, B_k (tape)
+    const void* Abar1; const void* Bbar1; // adjoints of A_{k+1}, B_{k+1}
+    void* Abar0; void* Bbar0;             // adjoints of A_k, B_k (out)
+    double* partI;                        // nwg_row x sI x R
+    double* partJ;                        // nwg_col x sJ x R
+    double* partz;                        // nwg_row + nwg_col
+    int32_t nwg_row, nwg_col;
+    // forward SVD outputs of this step (tape)
+    const double* Wt;                     // sI x R  (orthonormal left basis)
+    const double* Q;                      // sJ x R  (orthonormal right basis)
+    const double* Kc;                     // R x R   (H_r(M) = Wt Kc Q^T)
+    const double* TAd;                    // R x R   (Ly^-T: A_{k+1} = C Q Ly^-T)
+    const double* M;                      // sI x sJ core
+    // adjoint-of-the-core workspace and outputs
+    double* Mperp;                        // sI16 x sJ16: M - W_r Sigma V_r^T, zero padded
+    double* Wr; double* Vr;               // sI x R, sJ x R singular vectors (columns >= r zero)
+    double* Tp;                           // sJ x R: Q Ly^-T
+    double* X1; double* X2;               // sI x R, sJ x R: M_bar = X1 V_r^T + W_r X2^T
+    double* P1; double* P2;               // sI x R, sJ x R workspace
+    double* dz;                           // this step's zeta gradient (one value)
+    int32_t* flags;                       // bit 0: CG did not converge, bit 1: rank < r
+};
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_transpose(const void* src, int64_t lds, void* dst, int64_t ldd,
                             int64_t rows, int64_t cols, int elem_bytes, hipStream_t s);
 hipError_t launch_core(const CoreArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s);
+// Batch of nb cores, arr_dev[b] per core (device array); G in {1, 2, 4, 8}, P = 16.
+hipError_t launch_svd_batch(const SvdArgs* arr_dev, int nb, int G, int P, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
@@ -195,5 +245,20 @@ hipError_t launch_upinv(const double* V, const double* TA, const double* W, int 
                         void* out, int dtype, hipStream_t s);
 hipError_t launch_sparse_full(const SparseArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_alg2(const Alg2Args& a, hipStream_t s);
+// unrolled mode
+hipError_t launch_ucore(const CoreArgs* arr, const int32_t* off, int nb, int total_blocks, const double* zk,
+                        double tau_rel, int dtype, int R, hipStream_t s);
+hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total_blocks, int max_s,
+                        const double* zk, double tau_rel, int dtype, int R, hipStream_t s);
+int upass_segmax(int dtype, int R);
+hipError_t launch_uloss(const ULoss* arr, const int32_t* off, int nb, int total_blocks, int dtype, hipStream_t s);
+hipError_t launch_ulossadj(const ULoss* arr, const int32_t* off, int nb, int total_blocks, const double* dloss,
+                           int dtype, hipStream_t s);
+hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total_blocks,
+                         const double* zk, double tau_rel, int dtype, int R, hipStream_t s);
+hipError_t launch_ubsmall(const UBack* arr, int nb, int max_s16, int cg_max_it, double cg_tol, hipStream_t s);
+hipError_t launch_ubreduce(const UBack* arr, const int32_t* off, int nb, int total_blocks, int dtype, hipStream_t s);
+size_t ubsmall_lds_bytes(int max_s16);
+hipError_t launch_udzeta(const double* dz_inst, int nb, int K, double* dzeta, hipStream_t s);
 
 }  // namespace ircur

@@ -1,0 +1,247 @@
+// FP64 small-matrix helpers for one 256-thread workgroup: matrix-core tile
+// products with operands in LDS or global memory, Cholesky factorisation with
+// inverse, Cholesky-QR orthonormalisation, block reductions.  Shared by the
+// SVD kernels; each translation unit gets its own copy.
+#pragma once
+
+#include "ircur_internal.h"
+
+#include <stdint.h>
+
+namespace ircur {
+
+namespace {
+
+constexpr int NT = 256;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double fget(const void* p, int64_t i, int dt) {
+    if (dt == 0) return ((const double*)p)[i];
+    return (double)((const float*)p)[i];   // float factors (F32 and BF16 modes)
+}
+__device__ __forceinline__ void fput(void* p, int64_t i, double v, int dt) {
+    if (dt == 0) ((double*)p)[i] = v;
+    else ((float*)p)[i] = (float)v;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double rnd_unit(uint64_t salt, uint64_t i) {
+    const uint64_t h = mix64(salt + 0x9E3779B97F4A7C15ull * (i + 1));
+    return (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum_d(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// ------------------------------------------------------- MFMA (FP64) ---
+// One 16 x 16 output tile, acc += op(A) op(B) over k in [k0, k1) (multiples
+// of 4), operands in LDS.  Operand layout of v_mfma_f64_16x16x4f64: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; output element v of lane l is
+// C[l/16 + 4 v][l%16].
+// op(A)(i, k) = TA ? A[k*lda + i] : A[i*lda + k];  op(B)(k, j) = TB ? B[j*ldb + k] : B[k*ldb + j].
+template <bool TA, bool TB>
+__device__ __forceinline__ d4 mm_tile(const double* A, int lda, int i0, const double* B, int ldb, int j0,
+                                      int k0, int k1, d4 acc) {
+    const int l = threadIdx.x & 63;
+    const int ii = i0 + (l & 15), jj = j0 + (l & 15), kk = l >> 4;
+    // operands of 8 k-steps are loaded before their products are issued
+    for (int kb = k0; kb < k1; kb += 32) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = kb + 4 * u;
+            if (k < k1) {
+                av[u] = TA ? A[(k + kk) * lda + ii] : A[ii * lda + k + kk];
+                bv[u] = TB ? B[jj * ldb + k + kk] : B[(k + kk) * ldb + jj];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (kb + 4 * u < k1) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void tile_store(double* C, int ldc, int i0, int j0, d4 acc, int rows_valid) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + (l >> 4) + 4 * v;
+        C[i * ldc + j0 + (l & 15)] = (i < rows_valid) ? acc[v] : 0.0;
+    }
+}
+
+// C (m16 x P) = op(A) op(B) over K (multiple of 4), one 16-row group (all P
+// columns) per work item, the four waves taking groups round robin.  Rows of
+// C at or past rows_valid are written as zero.  C may alias op(A)'s rows when
+// TA is false (a group reads only its own rows before writing them).
+template <int P, bool TA, bool TB>
+__device__ void mm_rows(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                        int m16, int K, int rows_valid) {
+    const int w = threadIdx.x >> 6;
+    for (int t = w; t < (m16 >> 4); t += 4) {
+        const int i0 = t * 16;
+        d4 acc0 = {0.0, 0.0, 0.0, 0.0};
+        acc0 = mm_tile<TA, TB>(A, lda, i0, B, ldb, 0, 0, K, acc0);
+        if (P == 32) {
+            d4 acc1 = {0.0, 0.0, 0.0, 0.0};
+            acc1 = mm_tile<TA, TB>(A, lda, i0, B, ldb, 16, 0, K, acc1);
+            tile_store(C, ldc, i0, 0, acc0, rows_valid);
+            tile_store(C, ldc, i0, 16, acc1, rows_valid);
+        } else {
+            tile_store(C, ldc, i0, 0, acc0, rows_valid);
+        }
+    }
+}
+
+// P x P result of a long contraction over K4 (multiple of 4): the four waves
+// split K, the partial tiles are summed in LDS in a fixed order.
+template <int P, bool TA, bool TB>
+__device__ void mm_small(const double* A, int lda, const double* B, int ldb, double* C, int K4,
+                         double* scratch /* 4 * P * P */) {
+    const int w = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int ksteps = K4 >> 2;
+    const int per = (ksteps + 3) >> 2;
+    const int k0 = min(ksteps, w * per) * 4, k1 = min(ksteps, (w + 1) * per) * 4;
+    constexpr int nt = P / 16;
+#pragma unroll
+    for (int ti = 0; ti < nt; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < nt; ++tj) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mm_tile<TA, TB>(A, lda, ti * 16, B, ldb, tj * 16, k0, k1, acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                scratch[w * P * P + (ti * 16 + (l >> 4) + 4 * v) * P + tj * 16 + (l & 15)] = acc[v];
+        }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * P; e += NT)
+        C[e] = ((scratch[e] + scratch[P * P + e]) + scratch[2 * P * P + e]) + scratch[3 * P * P + e];
+    __syncthreads();
+}
+
+// ------------------------------------------------ small factorisations ---
+// Cholesky G = L L^T of a P x P symmetric positive semidefinite matrix and
+// Linv = L^-1, by the first wave with lane i holding row i in registers.  A
+// pivot <= tol * max_j G_jj marks a dependent direction: its column of L and
+// row of Linv are zero and dead[j] = 1.  G, L, Linv are P x P in LDS.
+template <int P>
+__device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, double tol) {
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        double a[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) a[j] = (i < P) ? G[i * P + j] : 0.0;
+        double dmax = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) dmax = fmax(dmax, readlane_d(a[j], j));
+        const double thr = tol * dmax;
+        double inv_d[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const double d = readlane_d(a[j], j);
+            const bool dj = !(d > thr);
+            const double piv = dj ? 0.0 : __builtin_sqrt(d);
+            const double inv = dj ? 0.0 : 1.0 / piv;
+            inv_d[j] = inv;
+            const double lij = (i > j) ? a[j] * inv : ((i == j) ? piv : 0.0);
+            a[j] = lij;
+#pragma unroll
+            for (int k = j + 1; k < P; ++k) {
+                const double lk = readlane_d(lij, k);
+                if (i >= k) a[k] = __builtin_fma(-lij, lk, a[k]);
+            }
+            if (i == 0) dead[j] = dj ? 1 : 0;
+        }
+        // Linv by forward elimination on [L | I], rows in order
+        double x[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) x[j] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (i == k) {
+#pragma unroll
+                for (int j = 0; j <= k; ++j) x[j] *= inv_d[k];
+            }
+            if (i > k) {
+                const double lik = a[k];
+#pragma unroll
+                for (int j = 0; j <= k; ++j) x[j] = __builtin_fma(-lik, readlane_d(x[j], k), x[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j <= k; ++j) (void)readlane_d(x[j], k);
+            }
+        }
+        if (i < P) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                L[i * P + j] = (j <= i) ? a[j] : 0.0;
+                Linv[i * P + j] = (j <= i) ? x[j] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Orthonormalise the first `live` columns of X (m16 x P, LDS, row stride P)
+// in place by Cholesky QR (X <- X Linv^T with X^T X = L L^T), repeated while
+// max |X^T X - I| exceeds 1e-13 (at most three passes).  A dependent column
+// is refilled with pseudo-random entries and the pass repeated; columns at or
+// past `live` stay zero.
+template <int P>
+__device__ void orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
+                               double* Li, int* dead, double* scratch, double* red, uint64_t salt) {
+    for (int pass = 0; pass < 4; ++pass) {
+        mm_small<P, true, false>(X, P, X, P, Gs, m16, scratch);
+        // orthonormality defect
+        double dev = 0.0;
+        for (int e = threadIdx.x; e < P * P; e += NT) {
+            const int i = e / P, j = e - i * P;
+            if (i < live && j < live) dev = fmax(dev, fabs(Gs[e] - (i == j ? 1.0 : 0.0)));
+        }
+        for (int off = 32; off >= 1; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+        __syncthreads();
+        const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        __syncthreads();
+        if (!(dmax > 1e-13) && pass > 0) break;
+        chol_inv<P>(Gs, Ls, Li, dead, 1e-14);
+        mm_rows<P, false, true>(X, P, Li, P, X, P, m16, P, rows_valid);
+        __syncthreads();
+        int nd = 0;
+        for (int j = 0; j < live; ++j) nd += dead[j];
+        if (nd > 0) {
+            for (int e = threadIdx.x; e < rows_valid * P; e += NT) {
+                const int c = e % P;
+                if (c < live && dead[c]) X[e] = rnd_unit(salt ^ (0x5bd1e995ull * (uint64_t)(pass + 1)), (uint64_t)e);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+}  // namespace ircur

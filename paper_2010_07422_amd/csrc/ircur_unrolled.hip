@@ -1,0 +1,903 @@
+// Unrolled, differentiable IRCUR over a batch of independent instances.
+//
+// The paper's iteration (Algorithm 1) uses the hard threshold of eq. (4).
+// The unrolled mode runs K iterations with one threshold zeta_k per
+// iteration and the gate S(x) = x g, g = sigmoid((|x| - zeta) / (tau_rel zeta))
+// (tau_rel = 0: eq. (4) exactly), so that a loss of the final estimate is
+// differentiable in the zeta_k.  Per instance,
+//     loss = ||A_K B_K - W* V*^T||_F / ||W* V*^T||_F .
+//
+// Forward, per step k (one launch per stage for the whole batch):
+//   ucore   M = [D - S]_{I,J} with the gated S (and the two MFMA layouts)
+//   svd     the batched Phase II core kernel (factored pseudo-inverse)
+//   upass   A_{k+1} = C Q Ly^-T, B_{k+1} = Wt^T R with the same gate
+// then the loss from factor Grams.
+//
+// Reverse, per step k = K-1 .. 0, from Abar = dloss/dA_{k+1}, Bbar = dloss/dB_{k+1}:
+//   ubpass(1)  Wbar = R Bbar^T (sI x R) and Tbar = C^T Abar (sJ x R), recomputing
+//              the gathered rows and columns of this step from D
+//   ubsmall    adjoint of the core, one workgroup per instance: singular triplets
+//              of H_r(M) from Kc, the projections P1 = V_r^T Ubar = Sigma U_k^T Wbar^T
+//              and P2 = Ubar W_r = Tbar U_k of the adjoint of U^+, resolvent solves
+//              (sigma_c^2 I - M_perp M_perp^T) x = P1 (and the M^T M side) by
+//              conjugate gradients on the complement of the top-r subspaces, and
+//              Mbar = X1 V_r^T + W_r X2^T (first-order perturbation of the
+//              truncated pseudo-inverse)
+//   ubpass(2)  the gate adjoint: dloss/dzeta_k, Abar_k and Bbar_k
+//   ubreduce   adds the per-row partials of Abar_k[I, :], Bbar_k[:, J] and zeta.
+#include "ircur_device.h"
+#include "ircur_small.h"
+
+#include <stdint.h>
+
+namespace ircur {
+
+namespace {
+
+__device__ __forceinline__ int find_inst(const int32_t* __restrict__ off, int nb, int x) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float round_down_f(double z) {
+    float f = (float)z;
+    if ((double)f > z) f = nextafterf(f, -__builtin_inff());
+    return f;
+}
+
+// S = x g and its derivatives: g, dS/dx, dS/dzeta (tauz = tau_rel zeta).
+template <typename F>
+__device__ __forceinline__ void gate_derivs(F x, F zeta, F tauz, F& g, F& dSdx, F& dSdz) {
+    const F ax = x < F(0) ? -x : x;
+    g = F(1) / (F(1) + exp_t(-(ax - zeta) / tauz));
+    const F gg = g * (F(1) - g);
+    dSdx = g + ax * gg / tauz;
+    dSdz = -x * ax * gg / (tauz * zeta);
+}
+
+// ------------------------------------------------------------ forward ---
+
+template <typename T, typename F, int R, bool GATE>
+__global__ __launch_bounds__(256) void ucore_kernel(const CoreArgs* __restrict__ arr, const int32_t* __restrict__ off,
+                                                    int nb, const double* __restrict__ zk, double tau_rel) {
+    const int b = find_inst(off, nb, blockIdx.x);
+    const CoreArgs& a = arr[b];
+    const int local = blockIdx.x - off[b];
+    if (local == 0 && threadIdx.x == 0) a.st->bar_ctr = 0u;
+    const int64_t idx = (int64_t)local * 256 + threadIdx.x;
+    if (idx >= (int64_t)a.sI * a.sJ) return;
+    const int ai = (int)(idx / a.sJ), bj = (int)(idx - (int64_t)ai * a.sJ);
+    const int64_t i = a.I[ai], j = a.J[bj];
+    const T* __restrict__ D = (const T*)a.D;
+    const F* __restrict__ At = (const F*)a.At;
+    const F* __restrict__ B = (const F*)a.B;
+    const F d = ld<T, F>(D + i * a.ldD + j);
+    F dot = F(0);
+#pragma unroll
+    for (int c = 0; c < R; ++c) dot = fmaT(At[c * a.n1 + i], B[c * a.n2 + j], dot);
+    const double zeta = *zk;
+    F v;
+    if (GATE) {
+        const F x = d - dot;
+        v = d - x * gate_value<F>(x, (F)zeta, (F)(tau_rel * zeta));
+    } else {
+        bool o;
+        v = entry_value<F>(d, dot, zeta, round_down_f(zeta), &o);
+    }
+    const double mv = (double)v;
+    a.M[idx] = mv;
+    const int sJ16 = ((a.sJ + 15) / 16) * 16, sI16 = ((a.sI + 15) / 16) * 16;
+    a.MA[((size_t)(ai >> 4) * (sJ16 >> 2) + (bj >> 2)) * 64 + ((bj & 3) << 4) + (ai & 15)] = mv;
+    a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
+}
+
+template <typename T, typename F, int R, bool GATE>
+__global__ __launch_bounds__(256) void upass_kernel(const PassArgs* __restrict__ arr, const int32_t* __restrict__ off,
+                                                    int nb, const double* __restrict__ zk, double tau_rel) {
+    __shared__ F red[4][R][64];
+    __shared__ double redz[4][64];
+    __shared__ double redd[4][64];
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int b = find_inst(off, nb, blockIdx.x);
+    const PassArgs& a = arr[b];
+    const int local = blockIdx.x - off[b];
+    const double zeta = *zk;
+    const float zf = round_down_f(zeta);
+    const F tz = (F)(tau_rel * zeta);
+    if (local < a.side[0].nwg)
+        side_body<T, F, R, false, GATE>(a.side[0], local, zeta, zf, red, redz, redd, (F*)dyn, a.segmax, tz);
+    else
+        side_body<T, F, R, false, GATE>(a.side[1], local - a.side[0].nwg, zeta, zf, red, redz, redd, (F*)dyn,
+                                        a.segmax, tz);
+}
+
+// ---------------------------------------------------------------- loss ---
+
+constexpr int kGramRows = 128;
+
+template <typename F>
+__global__ __launch_bounds__(256) void ugram_kernel(const ULoss* __restrict__ arr, const int32_t* __restrict__ off,
+                                                    int nb) {
+    __shared__ double ys[kGramRows][33];
+    const int b = find_inst(off, nb, blockIdx.x);
+    const ULoss& L = arr[b];
+    const int local = blockIdx.x - off[b];
+    const int side = local < L.nwgA ? 0 : 1;
+    const int w = side == 0 ? local : local - L.nwgA;
+    const int nw = side == 0 ? L.nwgA : L.nwgB;
+    const int64_t n = side == 0 ? L.n1 : L.n2;
+    const F* __restrict__ X = (const F*)(side == 0 ? L.At : L.B);   // R x n
+    const F* __restrict__ S = (const F*)(side == 0 ? L.Ws : L.Vs);  // n x r
+    const int R = L.R, r = L.r, R2 = 2 * R;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t ch = w; ch * kGramRows < n; ch += nw) {
+        const int t = threadIdx.x;
+        if (t < kGramRows) {
+            const int64_t i = ch * kGramRows + t;
+            for (int c = 0; c < R; ++c) {
+                ys[t][c] = i < n ? (double)X[c * n + i] : 0.0;
+                ys[t][R + c] = (i < n && c < r) ? (double)S[i * r + c] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            if (e < R2 * R2) {
+                const int c = e / R2, d = e - c * R2;
+                double s = acc[q];
+                for (int row = 0; row < kGramRows; ++row) s = __builtin_fma(ys[row][c], ys[row][d], s);
+                acc[q] = s;
+            }
+        }
+        __syncthreads();
+    }
+    double* out = L.gpart + (size_t)local * R2 * R2;
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < R2 * R2) out[e] = acc[q];
+    }
+}
+
+// One workgroup per instance: reduce the Gram partials; the loss from
+//   ||A B||^2 = <A^T A, B B^T>,  <A B, W* V*^T> = <A^T W*, B V*>,
+//   ||W* V*^T||^2 = <W*^T W*, V*^T V*>.
+__global__ __launch_bounds__(256) void uloss_kernel(const ULoss* __restrict__ arr) {
+    __shared__ double part[3][256];
+    const ULoss& L = arr[blockIdx.x];
+    const int R = L.R, r = L.r, R2 = 2 * R, Q2 = R2 * R2;
+    for (int e = threadIdx.x; e < 2 * Q2; e += 256) {
+        const int side = e / Q2, f = e - side * Q2;
+        const int w0 = side == 0 ? 0 : L.nwgA, w1 = side == 0 ? L.nwgA : L.nwgA + L.nwgB;
+        double s = 0.0;
+        for (int w = w0; w < w1; ++w) s += L.gpart[(size_t)w * Q2 + f];
+        L.gsum[e] = s;
+    }
+    __syncthreads();
+    const double* GA = L.gsum;
+    const double* GB = L.gsum + Q2;
+    double ab = 0.0, cr = 0.0, ls = 0.0;
+    for (int e = threadIdx.x; e < Q2; e += 256) {
+        const int c = e / R2, d = e - c * R2;
+        if (c < R && d < R) ab = __builtin_fma(GA[e], GB[e], ab);
+        else if (c < R && d >= R && d - R < r) cr = __builtin_fma(GA[e], GB[e], cr);
+        else if (c >= R && d >= R && c - R < r && d - R < r) ls = __builtin_fma(GA[e], GB[e], ls);
+    }
+    part[0][threadIdx.x] = ab;
+    part[1][threadIdx.x] = cr;
+    part[2][threadIdx.x] = ls;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e2 = part[0][0] - 2.0 * part[1][0] + part[2][0];
+        const double l2 = part[2][0];
+        const double loss = l2 > 0.0 ? __builtin_sqrt((e2 > 0.0 ? e2 : 0.0) / l2) : 0.0;
+        L.loss[0] = loss;
+        L.gsum[2 * Q2] = loss;
+        L.gsum[2 * Q2 + 1] = l2;
+    }
+}
+
+// dloss/dA_K = s (A G_BB - W* (B V*)^T),  dloss/dB_K = s (G_AA B - (A^T W*) V*^T),
+// s = dloss_b / (||E|| ||L*||).
+template <typename F>
+__global__ __launch_bounds__(256) void ulossadj_kernel(const ULoss* __restrict__ arr, const int32_t* __restrict__ off,
+                                                       int nb, const double* __restrict__ dloss) {
+    const int b = find_inst(off, nb, blockIdx.x);
+    const ULoss& L = arr[b];
+    const int local = blockIdx.x - off[b];
+    const int R = L.R, r = L.r, R2 = 2 * R, Q2 = R2 * R2;
+    const int nA = (int)((L.n1 + 255) / 256);
+    const double loss = L.gsum[2 * Q2], l2 = L.gsum[2 * Q2 + 1];
+    const double den = loss * l2;                       // ||E|| ||L*|| = loss ||L*||^2
+    const double sc = (den > 0.0 ? 1.0 / den : 0.0) * (dloss ? dloss[b] : 1.0);
+    const int side = local < nA ? 0 : 1;
+    const int64_t n = side == 0 ? L.n1 : L.n2;
+    const int64_t i = (int64_t)(side == 0 ? local : local - nA) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double* G = L.gsum + (side == 0 ? Q2 : 0);   // side A uses G_B, side B uses G_A
+    const F* __restrict__ X = (const F*)(side == 0 ? L.At : L.B);
+    const F* __restrict__ S = (const F*)(side == 0 ? L.Ws : L.Vs);
+    F* __restrict__ out = (F*)(side == 0 ? L.Abar : L.Bbar);
+    double x[32], sv[32];
+    for (int c = 0; c < R; ++c) x[c] = (double)X[c * n + i];
+    for (int f = 0; f < r; ++f) sv[f] = (double)S[i * r + f];
+    for (int c = 0; c < R; ++c) {
+        double v = 0.0;
+        for (int e = 0; e < R; ++e) v = __builtin_fma(x[e], G[e * R2 + c], v);
+        for (int f = 0; f < r; ++f) v = __builtin_fma(-sv[f], G[c * R2 + R + f], v);
+        out[c * n + i] = (F)(sc * v);
+    }
+}
+
+// ------------------------------------------------------------ reverse ---
+
+// Phase 1: per sampled row a (column b) the partial sums over this block's
+// 64 outputs of  R[a, j] Bbar[c, j]  (C[i, b] Abar[i, c]).
+// Phase 2: the gate adjoint.  Row side, output j:
+//     Rbar[a, j] = Wt[a, :] Bbar[:, j] + (j = J_b ? X1[a, :] V_r[b, :] + W_r[a, :] X2[b, :] : 0)
+//     Xbar = -Rbar dS/dx,  zeta_bar += -Rbar dS/dzeta,
+//     Bbar_k[:, j] = -sum_a A_k[I_a, :]^T Xbar (dense),  Abar_k[I_a, :] partial -sum_j Xbar B_k[:, j]^T
+// and the column side with Cbar[i, b] = Abar[i, :] Tp[b, :] and the roles of
+// the factors exchanged.
+template <typename T, typename F, int R, bool GATE, int PH>
+__global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ arr, const int32_t* __restrict__ off,
+                                                     int nb, const double* __restrict__ zk, double tau_rel) {
+    __shared__ F red[4][R][64];
+    __shared__ double zred[4];
+    const int b = find_inst(off, nb, blockIdx.x);
+    const UBack& u = arr[b];
+    const int local = blockIdx.x - off[b];
+    const double zeta = *zk;
+    const float zf = round_down_f(zeta);
+    const F zF = (F)zeta;
+    const F tz = (F)(tau_rel * zeta);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const bool rowside = local < u.nwg_row;
+    const int wg = rowside ? local : local - u.nwg_row;
+    const int64_t n = rowside ? u.n2 : u.n1;
+    const int s = rowside ? u.sI : u.sJ;
+    const int64_t col = (int64_t)wg * 64 + lane;
+    const bool valid = col < n;
+    const int64_t cc = valid ? col : 0;
+    const T* __restrict__ X = (const T*)(rowside ? u.D : u.Dt);
+    const int64_t ldX = rowside ? u.ldD : u.ldDt;
+    const int32_t* __restrict__ rows = rowside ? u.I : u.J;
+    const F* __restrict__ At = (const F*)u.At;
+    const F* __restrict__ Bk = (const F*)u.B;
+    const F* __restrict__ P = rowside ? Bk : At;
+    const F* __restrict__ Pb = (const F*)(rowside ? u.Bbar1 : u.Abar1);
+    const F* __restrict__ Qf = rowside ? At : Bk;
+    const int64_t nq = rowside ? u.n1 : u.n2;
+    double* __restrict__ part = rowside ? u.partI : u.partJ;
+    F p[R], pb[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        p[c] = P[c * n + cc];
+        pb[c] = Pb[c * n + cc];
+    }
+    F vb[R], xb[R];
+    bool inJ = false;
+    if (PH == 2 && rowside) {
+        const int bp = valid ? u.posJ[col] : -1;
+        inJ = bp >= 0;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            vb[c] = inJ ? (F)u.Vr[(int64_t)bp * R + c] : F(0);
+            xb[c] = inJ ? (F)u.X2[(int64_t)bp * R + c] : F(0);
+        }
+    }
+    F acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = F(0);
+    double zacc = 0.0;
+    const int chunk = (s + 3) >> 2;
+    const int a_begin = wave * chunk;
+    const int a_end = min(s, a_begin + chunk);
+    constexpr int U = 4;
+    for (int a0 = a_begin; a0 < a_end; a0 += U) {
+        F dv[U];
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int a = min(a0 + uu, a_end - 1);
+            dv[uu] = ld<T, F>(X + (int64_t)rows[a] * ldX + cc);
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int a = a0 + uu;
+            if (a < a_end) {
+                const int64_t rix = rows[a];
+                F q[R];
+#pragma unroll
+                for (int c = 0; c < R; ++c) q[c] = Qf[c * nq + rix];
+                const F d = valid ? dv[uu] : F(0);
+                F dot = F(0);
+#pragma unroll
+                for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c], dot);
+                const F x = d - dot;
+                F g, dSdx, dSdz;
+                if (GATE) {
+                    gate_derivs<F>(x, zF, tz, g, dSdx, dSdz);
+                } else {
+                    g = above(x < F(0) ? -x : x, zeta, zf) ? F(1) : F(0);
+                    dSdx = g;
+                    dSdz = F(0);
+                }
+                if (PH == 1) {
+                    const F v = GATE ? d - x * g : (g != F(0) ? d - x : d);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        double sc = valid ? (double)v * (double)pb[c] : 0.0;
+                        sc = wave_sum(sc);
+                        if (lane == 0) part[((int64_t)wg * s + a) * R + c] = sc;
+                    }
+                } else {
+                    F ybar = F(0);
+                    if (rowside) {
+#pragma unroll
+                        for (int c = 0; c < R; ++c) ybar = fmaT((F)u.Wt[(int64_t)a * R + c], pb[c], ybar);
+                        if (inJ) {
+#pragma unroll
+                            for (int c = 0; c < R; ++c) {
+                                ybar = fmaT((F)u.X1[(int64_t)a * R + c], vb[c], ybar);
+                                ybar = fmaT((F)u.Wr[(int64_t)a * R + c], xb[c], ybar);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < R; ++c) ybar = fmaT(pb[c], (F)u.Tp[(int64_t)a * R + c], ybar);
+                    }
+                    const F xbar = -ybar * dSdx;
+                    if (valid) zacc += -(double)ybar * (double)dSdz;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] = fmaT(q[c], xbar, acc[c]);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        double sc = valid ? (double)xbar * (double)p[c] : 0.0;
+                        sc = wave_sum(sc);
+                        if (lane == 0) part[((int64_t)wg * s + a) * R + c] = -sc;
+                    }
+                }
+            }
+        }
+    }
+    if (PH == 2) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) red[wave][c][lane] = acc[c];
+        const double zw = wave_sum(zacc);
+        if (lane == 0) zred[wave] = zw;
+        __syncthreads();
+        if (wave == 0) {
+            F* __restrict__ out = (F*)(rowside ? u.Bbar0 : u.Abar0);
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < R; ++c)
+                    out[c * n + col] = -(((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane]);
+            }
+            if (lane == 0) u.partz[local] = ((zred[0] + zred[1]) + zred[2]) + zred[3];
+        }
+    }
+}
+
+// ---- adjoint of the core (one workgroup per instance) ---------------------
+
+// Column dot products of two m x 16 LDS blocks (row stride 16), fixed order.
+__device__ void coldot16(const double* A, const double* B, int m, double* part, double* out) {
+    const int c = threadIdx.x & 15, pp = threadIdx.x >> 4;
+    double s = 0.0;
+    for (int a = pp; a < m; a += 16) s = __builtin_fma(A[a * 16 + c], B[a * 16 + c], s);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += part[q * 16 + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// One-sided Jacobi SVD of the leading r x r block of K (16 x 16, LDS) by the
+// first wave, lane i owning row i of K and of Vm.  On return the columns of
+// K are U Sigma and Vm holds V.
+__device__ void jacobi16(double* K, double* Vm, int r) {
+    const int i = threadIdx.x;
+    if (i < 64) {
+        if (i < 16)
+            for (int c = 0; c < 16; ++c) Vm[i * 16 + c] = (i == c) ? 1.0 : 0.0;
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            int rot = 0;
+            for (int pp = 0; pp < r - 1; ++pp) {
+                for (int qq = pp + 1; qq < r; ++qq) {
+                    const double kp = i < r ? K[i * 16 + pp] : 0.0, kq = i < r ? K[i * 16 + qq] : 0.0;
+                    const double al = wave_sum(kp * kp), be = wave_sum(kq * kq), ga = wave_sum(kp * kq);
+                    if (!(fabs(ga) > 1e-15 * __builtin_sqrt(al * be))) continue;
+                    ++rot;
+                    const double zt = (be - al) / (2.0 * ga);
+                    const double t = (zt >= 0.0 ? 1.0 : -1.0) / (fabs(zt) + __builtin_sqrt(1.0 + zt * zt));
+                    const double cs = 1.0 / __builtin_sqrt(1.0 + t * t), sn = cs * t;
+                    if (i < r) {
+                        K[i * 16 + pp] = cs * kp - sn * kq;
+                        K[i * 16 + qq] = sn * kp + cs * kq;
+                        const double vp = Vm[i * 16 + pp], vq = Vm[i * 16 + qq];
+                        Vm[i * 16 + pp] = cs * vp - sn * vq;
+                        Vm[i * 16 + qq] = sn * vp + cs * vq;
+                    }
+                }
+            }
+            if (rot == 0) break;
+        }
+    }
+    __syncthreads();
+}
+
+// Conjugate gradients, one system per column c < r:
+//     (sig2[c] I - A B) x_c = rhs_c    (op = A B: the two products of M_perp)
+// on m16 x 16 LDS blocks X (solution), Rr (rhs in, residual out), Pp, AP,
+// with Tm (mo16 x 16) for the inner product.  Returns 1 if some column did
+// not reach the tolerance.
+template <bool LEFT>
+__device__ int cg_solve(const double* Mp, int sI16, int sJ16, int sI, int sJ, const double* sig2, int r,
+                        double* X, double* Rr, double* Pp, double* AP, double* Tm, double* part, double* cols,
+                        int max_it, double tol) {
+    const int m16 = LEFT ? sI16 : sJ16, m = LEFT ? sI : sJ;
+    double* rr = cols;          // 16
+    double* bb = cols + 16;
+    double* pap = cols + 32;
+    double* rn = cols + 48;
+    double* flag = cols + 64;
+    for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+        X[e] = 0.0;
+        Pp[e] = Rr[e];
+    }
+    __syncthreads();
+    coldot16(Rr, Rr, m16, part, rr);
+    if (threadIdx.x < 16) bb[threadIdx.x] = rr[threadIdx.x];
+    __syncthreads();
+    int it = 0;
+    int fail = 0;
+    for (; it < max_it; ++it) {
+        // convergence test (every thread reads the same LDS values)
+        bool done = true;
+        for (int c = 0; c < r; ++c)
+            if (rr[c] > tol * tol * bb[c]) done = false;
+        if (done) break;
+        // AP = sig2 P - Mp (Mp^T P)   (LEFT)   or   sig2 P - Mp^T (Mp P)
+        if (LEFT) {
+            mm_rows<16, true, false>(Mp, sJ16, Pp, 16, Tm, 16, sJ16, sI16, sJ);
+            __syncthreads();
+            mm_rows<16, false, false>(Mp, sJ16, Tm, 16, AP, 16, sI16, sJ16, sI);
+        } else {
+            mm_rows<16, false, false>(Mp, sJ16, Pp, 16, Tm, 16, sI16, sJ16, sI);
+            __syncthreads();
+            mm_rows<16, true, false>(Mp, sJ16, Tm, 16, AP, 16, sJ16, sI16, sJ);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+            const int c = e & 15;
+            AP[e] = (c < r && (e >> 4) < m) ? __builtin_fma(sig2[c], Pp[e], -AP[e]) : 0.0;
+        }
+        __syncthreads();
+        coldot16(Pp, AP, m16, part, pap);
+        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+            const int c = e & 15;
+            const double al = (c < r && pap[c] > 0.0) ? rr[c] / pap[c] : 0.0;
+            X[e] = __builtin_fma(al, Pp[e], X[e]);
+            Rr[e] = __builtin_fma(-al, AP[e], Rr[e]);
+        }
+        __syncthreads();
+        coldot16(Rr, Rr, m16, part, rn);
+        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+            const int c = e & 15;
+            const double be = (c < r && rr[c] > 0.0) ? rn[c] / rr[c] : 0.0;
+            Pp[e] = __builtin_fma(be, Pp[e], Rr[e]);
+        }
+        __syncthreads();
+        if (threadIdx.x < 16) rr[threadIdx.x] = rn[threadIdx.x];
+        __syncthreads();
+    }
+    if (it >= max_it) fail = 1;
+    (void)flag;
+    return fail;
+}
+
+__global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ arr, int max_it, double tol) {
+    extern __shared__ double smem[];
+    const UBack& u = arr[blockIdx.x];
+    const int R = u.R, r = u.r, sI = u.sI, sJ = u.sJ;
+    const int sI16 = ((sI + 15) / 16) * 16, sJ16 = ((sJ + 15) / 16) * 16;
+    const int m16 = sI16 > sJ16 ? sI16 : sJ16;
+    double* B0 = smem;                  // m16 x 16 each
+    double* B1 = B0 + m16 * 16;
+    double* B2 = B1 + m16 * 16;
+    double* B3 = B2 + m16 * 16;
+    double* B4 = B3 + m16 * 16;
+    double* K = B4 + m16 * 16;          // 16 x 16
+    double* Vm = K + 256;
+    double* Uk = Vm + 256;
+    double* Vk = Uk + 256;
+    double* Urr = Vk + 256;
+    double* part = Urr + 256;           // 256
+    double* cols = part + 256;          // 80
+    double* sig = cols + 80;            // 16
+    double* sig2 = sig + 16;            // 16
+    int* order = (int*)(sig2 + 16);     // 16
+    const int tid = threadIdx.x;
+
+    // singular triplets of H_r(M) = Wt Kc Q^T:  Kc = U_k Sigma V_k^T
+    for (int e = tid; e < 256; e += NT) {
+        const int i = e >> 4, j = e & 15;
+        K[e] = (i < R && j < R) ? u.Kc[i * R + j] : 0.0;
+    }
+    __syncthreads();
+    jacobi16(K, Vm, r);
+    if (tid < 16) {
+        double s2 = 0.0;
+        for (int i = 0; i < r; ++i) s2 = __builtin_fma(K[i * 16 + tid], K[i * 16 + tid], s2);
+        part[tid] = tid < r ? __builtin_sqrt(s2) : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int c = 0; c < 16; ++c) order[c] = c;
+        for (int x = 0; x < r; ++x)
+            for (int y = x + 1; y < r; ++y)
+                if (part[order[y]] > part[order[x]]) { const int t = order[x]; order[x] = order[y]; order[y] = t; }
+        for (int c = 0; c < 16; ++c) {
+            sig[c] = c < r ? part[order[c]] : 0.0;
+            sig2[c] = sig[c] * sig[c];
+        }
+        if (!(sig[r - 1] > 2.220446049250313e-16 * (double)(sI > sJ ? sI : sJ) * sig[0])) u.flags[0] |= 2;
+    }
+    __syncthreads();
+    for (int e = tid; e < 256; e += NT) {
+        const int i = e >> 4, c = e & 15;
+        const bool ok = c < r && sig[c] > 0.0;
+        Uk[e] = ok ? K[i * 16 + order[c]] / sig[c] : 0.0;
+        Vk[e] = ok ? Vm[i * 16 + order[c]] : 0.0;
+    }
+    __syncthreads();
+    // W_r = Wt U_k,  V_r = Q V_k,  Tp = Q Ly^-T
+    for (int e = tid; e < sI * R; e += NT) {
+        const int a = e / R, c = e - a * R;
+        double s = 0.0;
+        for (int f = 0; f < R; ++f) s = __builtin_fma(u.Wt[a * R + f], Uk[f * 16 + c], s);
+        u.Wr[e] = s;
+    }
+    for (int e = tid; e < sJ * R; e += NT) {
+        const int b = e / R, c = e - b * R;
+        double s = 0.0, t = 0.0;
+        for (int f = 0; f < R; ++f) {
+            s = __builtin_fma(u.Q[b * R + f], Vk[f * 16 + c], s);
+            t = __builtin_fma(u.Q[b * R + f], u.TAd[f * R + c], t);
+        }
+        u.Vr[e] = s;
+        u.Tp[e] = t;
+    }
+    // Wbar = sum of row partials (sI x R) into B0, Tbar (sJ x R) into B1
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int a = e >> 4, c = e & 15;
+        double s0 = 0.0, s1 = 0.0;
+        if (c < R && a < sI)
+            for (int w = 0; w < u.nwg_row; ++w) s0 += u.partI[((int64_t)w * sI + a) * R + c];
+        if (c < R && a < sJ)
+            for (int w = 0; w < u.nwg_col; ++w) s1 += u.partJ[((int64_t)w * sJ + a) * R + c];
+        B0[e] = s0;
+        B1[e] = s1;
+    }
+    __syncthreads();
+    // P1t = Wbar U_k Sigma (sI x r), P2 = Tbar U_k (sJ x r)
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int a = e >> 4, c = e & 15;
+        double s0 = 0.0, s1 = 0.0;
+        if (c < r) {
+            for (int f = 0; f < R; ++f) {
+                s0 = __builtin_fma(B0[a * 16 + f], Uk[f * 16 + c], s0);
+                s1 = __builtin_fma(B1[a * 16 + f], Uk[f * 16 + c], s1);
+            }
+        }
+        B2[e] = (a < sI) ? s0 * sig[c] : 0.0;
+        B3[e] = (a < sJ) ? s1 : 0.0;
+    }
+    __syncthreads();
+    // Urr = P1 W_r (r x r); M_perp = M - W_r Sigma V_r^T (padded, global)
+    {
+        const int c = tid >> 4, e = tid & 15;
+        double s = 0.0;
+        if (c < r && e < r)
+            for (int a = 0; a < sI; ++a) s = __builtin_fma(B2[a * 16 + c], u.Wr[a * R + e], s);
+        Urr[tid] = s;
+    }
+    for (int e = tid; e < sI16 * sJ16; e += NT) {
+        const int a = e / sJ16, b = e - a * sJ16;
+        double v = 0.0;
+        if (a < sI && b < sJ) {
+            v = u.M[(int64_t)a * sJ + b];
+            for (int c = 0; c < r; ++c) v = __builtin_fma(-u.Wr[a * R + c] * sig[c], u.Vr[b * R + c], v);
+        }
+        u.Mperp[e] = v;
+    }
+    // right-hand sides projected on the complements: P1t - W_r (W_r^T P1t), P2 - V_r (V_r^T P2)
+    {
+        const int c = tid >> 4, e = tid & 15;
+        double s0 = 0.0, s1 = 0.0;
+        if (c < r && e < r) {
+            for (int a = 0; a < sI; ++a) s0 = __builtin_fma(u.Wr[a * R + c], B2[a * 16 + e], s0);
+            for (int b = 0; b < sJ; ++b) s1 = __builtin_fma(u.Vr[b * R + c], B3[b * 16 + e], s1);
+        }
+        K[tid] = s0;    // W_r^T P1t  (r x r)
+        Vm[tid] = s1;   // V_r^T P2
+    }
+    __syncthreads();
+    // keep P2 (projected) in global P2; W side first
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int a = e >> 4, c = e & 15;
+        double w = 0.0, v = 0.0;
+        if (c < r) {
+            w = B2[e];
+            v = B3[e];
+            for (int f = 0; f < r; ++f) {
+                if (a < sI) w = __builtin_fma(-u.Wr[a * R + f], K[f * 16 + c], w);
+                if (a < sJ) v = __builtin_fma(-u.Vr[a * R + f], Vm[f * 16 + c], v);
+            }
+        }
+        B1[e] = (a < sI) ? w : 0.0;            // W-side rhs
+        if (a < sJ && c < R) u.P2[a * R + c] = (c < r) ? v : 0.0;
+    }
+    __syncthreads();
+    int fail = 0;
+    // W side:  (sig_c^2 I - M_perp M_perp^T) x_c = rhs_c
+    fail |= cg_solve<true>(u.Mperp, sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+    // Qm = x / sigma (into B0), then M_perp^T Qm (sJ x 16) into B4
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int c = e & 15;
+        B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;
+    }
+    __syncthreads();
+    mm_rows<16, true, false>(u.Mperp, sJ16, B0, 16, B4, 16, sJ16, sI16, sJ);
+    __syncthreads();
+    // stash Qm in P1 and M_perp^T Qm in X2 (global)
+    for (int e = tid; e < sI * R; e += NT) {
+        const int a = e / R, c = e - a * R;
+        u.P1[e] = B0[a * 16 + c];
+    }
+    for (int e = tid; e < sJ * R; e += NT) {
+        const int b = e / R, c = e - b * R;
+        u.X2[e] = B4[b * 16 + c];
+    }
+    __syncthreads();
+    // V side:  (sig_c^2 I - M_perp^T M_perp) y_c = rhs_c
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int a = e >> 4, c = e & 15;
+        B1[e] = (a < sJ && c < R) ? u.P2[a * R + c] : 0.0;
+    }
+    __syncthreads();
+    fail |= cg_solve<false>(u.Mperp, sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+    for (int e = tid; e < m16 * 16; e += NT) {
+        const int c = e & 15;
+        B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;   // Um
+    }
+    __syncthreads();
+    mm_rows<16, false, false>(u.Mperp, sJ16, B0, 16, B4, 16, sI16, sJ16, sI);   // M_perp Um (sI x 16)
+    __syncthreads();
+    // X1 = Qm Sigma + M_perp Um - W_r Sigma^-1 Urr Sigma^-1,  X2 = M_perp^T Qm + Um Sigma
+    for (int e = tid; e < sI * R; e += NT) {
+        const int a = e / R, c = e - a * R;
+        double v = 0.0;
+        if (c < r) {
+            v = __builtin_fma(u.P1[e], sig[c], B4[a * 16 + c]);
+            for (int f = 0; f < r; ++f) v = __builtin_fma(-u.Wr[a * R + f], Urr[f * 16 + c] / (sig[f] * sig[c]), v);
+        }
+        u.X1[e] = v;
+    }
+    for (int e = tid; e < sJ * R; e += NT) {
+        const int b = e / R, c = e - b * R;
+        u.X2[e] = c < r ? __builtin_fma(B0[b * 16 + c], sig[c], u.X2[e]) : 0.0;
+    }
+    if (tid == 0 && fail) u.flags[0] |= 1;
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void ubreduce_kernel(const UBack* __restrict__ arr, const int32_t* __restrict__ off,
+                                                       int nb) {
+    __shared__ double red[256];
+    const int b = find_inst(off, nb, blockIdx.x);
+    const UBack& u = arr[b];
+    const int local = blockIdx.x - off[b];
+    const int R = u.R;
+    const int nI = (u.sI * R + 255) / 256, nJ = (u.sJ * R + 255) / 256;
+    if (local < nI) {
+        const int e = local * 256 + threadIdx.x;
+        if (e < u.sI * R) {
+            const int a = e / R, c = e - a * R;
+            double s = 0.0;
+            for (int w = 0; w < u.nwg_row; ++w) s += u.partI[((int64_t)w * u.sI + a) * R + c];
+            F* A0 = (F*)u.Abar0;
+            const int64_t idx = (int64_t)c * u.n1 + u.I[a];
+            A0[idx] = (F)((double)A0[idx] + s);
+        }
+    } else if (local < nI + nJ) {
+        const int e = (local - nI) * 256 + threadIdx.x;
+        if (e < u.sJ * R) {
+            const int bb = e / R, c = e - bb * R;
+            double s = 0.0;
+            for (int w = 0; w < u.nwg_col; ++w) s += u.partJ[((int64_t)w * u.sJ + bb) * R + c];
+            F* B0 = (F*)u.Bbar0;
+            const int64_t idx = (int64_t)c * u.n2 + u.J[bb];
+            B0[idx] = (F)((double)B0[idx] + s);
+        }
+    } else {
+        double s = 0.0;
+        for (int w = threadIdx.x; w < u.nwg_row + u.nwg_col; w += 256) s += u.partz[w];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h >= 1; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) u.dz[0] = red[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void udzeta_kernel(const double* __restrict__ dz_inst, int nb, int K,
+                                                     double* __restrict__ dzeta) {
+    for (int k = threadIdx.x; k < K; k += 256) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += dz_inst[(int64_t)k * nb + b];
+        dzeta[k] = s;
+    }
+}
+
+// ----------------------------------------------------------- launchers ---
+
+template <typename T, typename F, int R>
+hipError_t ucore_r(const CoreArgs* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
+                   hipStream_t s) {
+    if (tau > 0.0) ucore_kernel<T, F, R, true><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+    else ucore_kernel<T, F, R, false><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+    return hipGetLastError();
+}
+
+template <typename T, typename F, int R>
+int upass_segmax_r() {
+    constexpr int U = RowsInFlight<T>::value;
+    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
+    int segmax = (kPassStageBytes / (4 * rowbytes)) / U * U;
+    return segmax < U ? U : segmax;
+}
+
+template <typename T, typename F, int R>
+hipError_t upass_r(const PassArgs* arr, const int32_t* off, int nb, int total, int max_s, const double* zk,
+                   double tau, hipStream_t s) {
+    constexpr int U = RowsInFlight<T>::value;
+    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
+    const int segmax = upass_segmax_r<T, F, R>();
+    const int chunk = (max_s + 3) / 4;
+    const int seg = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    const size_t lds = (size_t)4 * seg * rowbytes;
+    static bool attr[2] = {false, false};
+    const int gi = tau > 0.0 ? 1 : 0;
+    const void* fn = tau > 0.0 ? (const void*)upass_kernel<T, F, R, true> : (const void*)upass_kernel<T, F, R, false>;
+    if (!attr[gi]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kPassStageBytes);
+        if (e != hipSuccess) return e;
+        attr[gi] = true;
+    }
+    if (tau > 0.0) upass_kernel<T, F, R, true><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
+    else upass_kernel<T, F, R, false><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
+    return hipGetLastError();
+}
+
+template <typename T, typename F, int R>
+hipError_t ubpass_r(int phase, const UBack* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
+                    hipStream_t s) {
+    if (phase == 1) {
+        if (tau > 0.0) ubpass_kernel<T, F, R, true, 1><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+        else ubpass_kernel<T, F, R, false, 1><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+    } else {
+        if (tau > 0.0) ubpass_kernel<T, F, R, true, 2><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+        else ubpass_kernel<T, F, R, false, 2><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+    }
+    return hipGetLastError();
+}
+
+#define IRCUR_URANK_SWITCH(FN, T, F, R, ...)                    \
+    switch (R) {                                                \
+        case 1: return FN<T, F, 1>(__VA_ARGS__);                \
+        case 2: return FN<T, F, 2>(__VA_ARGS__);                \
+        case 3: return FN<T, F, 3>(__VA_ARGS__);                \
+        case 4: return FN<T, F, 4>(__VA_ARGS__);                \
+        case 5: return FN<T, F, 5>(__VA_ARGS__);                \
+        case 6: return FN<T, F, 6>(__VA_ARGS__);                \
+        case 8: return FN<T, F, 8>(__VA_ARGS__);                \
+        case 10: return FN<T, F, 10>(__VA_ARGS__);              \
+        case 12: return FN<T, F, 12>(__VA_ARGS__);              \
+        case 16: return FN<T, F, 16>(__VA_ARGS__);              \
+        default: return hipErrorInvalidValue;                   \
+    }
+
+template <typename T, typename F, int R>
+int useg_r() { return upass_segmax_r<T, F, R>(); }
+
+}  // namespace
+
+hipError_t launch_ucore(const CoreArgs* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
+                        int dtype, int R, hipStream_t s) {
+    if (dtype == 0) { IRCUR_URANK_SWITCH(ucore_r, double, double, R, arr, off, nb, total, zk, tau, s) }
+    if (dtype == 1) { IRCUR_URANK_SWITCH(ucore_r, float, float, R, arr, off, nb, total, zk, tau, s) }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total, int max_s, const double* zk,
+                        double tau, int dtype, int R, hipStream_t s) {
+    if (dtype == 0) { IRCUR_URANK_SWITCH(upass_r, double, double, R, arr, off, nb, total, max_s, zk, tau, s) }
+    if (dtype == 1) { IRCUR_URANK_SWITCH(upass_r, float, float, R, arr, off, nb, total, max_s, zk, tau, s) }
+    return hipErrorInvalidValue;
+}
+
+int upass_segmax(int dtype, int R) {
+    auto f = [&]() -> int {
+        if (dtype == 0) { IRCUR_URANK_SWITCH(useg_r, double, double, R) }
+        IRCUR_URANK_SWITCH(useg_r, float, float, R)
+    };
+    return f();
+}
+
+hipError_t launch_uloss(const ULoss* arr, const int32_t* off, int nb, int total, int dtype, hipStream_t s) {
+    if (dtype == 0) ugram_kernel<double><<<total, 256, 0, s>>>(arr, off, nb);
+    else ugram_kernel<float><<<total, 256, 0, s>>>(arr, off, nb);
+    uloss_kernel<<<nb, 256, 0, s>>>(arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ulossadj(const ULoss* arr, const int32_t* off, int nb, int total, const double* dloss, int dtype,
+                           hipStream_t s) {
+    if (dtype == 0) ulossadj_kernel<double><<<total, 256, 0, s>>>(arr, off, nb, dloss);
+    else ulossadj_kernel<float><<<total, 256, 0, s>>>(arr, off, nb, dloss);
+    return hipGetLastError();
+}
+
+hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total, const double* zk,
+                         double tau, int dtype, int R, hipStream_t s) {
+    if (dtype == 0) { IRCUR_URANK_SWITCH(ubpass_r, double, double, R, phase, arr, off, nb, total, zk, tau, s) }
+    if (dtype == 1) { IRCUR_URANK_SWITCH(ubpass_r, float, float, R, phase, arr, off, nb, total, zk, tau, s) }
+    return hipErrorInvalidValue;
+}
+
+size_t ubsmall_lds_bytes(int max_s16) {
+    return ((size_t)5 * max_s16 * 16 + 5 * 256 + 256 + 80 + 32) * sizeof(double) + 16 * sizeof(int);
+}
+
+hipError_t launch_ubsmall(const UBack* arr, int nb, int max_s16, int cg_max_it, double cg_tol, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)ubsmall_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const size_t lds = ubsmall_lds_bytes(max_s16);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    ubsmall_kernel<<<nb, 256, lds, s>>>(arr, cg_max_it, cg_tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_ubreduce(const UBack* arr, const int32_t* off, int nb, int total, int dtype, hipStream_t s) {
+    if (dtype == 0) ubreduce_kernel<double><<<total, 256, 0, s>>>(arr, off, nb);
+    else ubreduce_kernel<float><<<total, 256, 0, s>>>(arr, off, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_udzeta(const double* dz_inst, int nb, int K, double* dzeta, hipStream_t s) {
+    udzeta_kernel<<<1, 256, 0, s>>>(dz_inst, nb, K, dzeta);
+    return hipGetLastError();
+}
+
+}  // namespace ircur

@@ -38,6 +38,15 @@ class IrcurError(RuntimeError):
         self.code = code
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("ldD", ctypes.c_int64),
+        ("sI", ctypes.c_int32), ("sJ", ctypes.c_int32),
+        ("D", ctypes.c_void_p), ("Dt", ctypes.c_void_p), ("ldDt", ctypes.c_int64),
+        ("Wstar", ctypes.c_void_p), ("Vstar", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -67,6 +76,15 @@ _SIGS = {
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
     "ircur_get_phase_profile": (ctypes.c_int, [_P, _DP]),
+    "ircur_unrolled_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Instance), ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P]),
+    "ircur_unrolled_forward": (ctypes.c_int, [_P, _P, _P]),
+    "ircur_backward": (ctypes.c_int, [_P, _P, _P]),
+    "ircur_unrolled_get_factors": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "ircur_unrolled_get_sets": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
+    "ircur_unrolled_status": (ctypes.c_int, [_P, _I32P]),
+    "ircur_unrolled_destroy": (None, [_P]),
+    "ircur_unrolled_last_error": (ctypes.c_char_p, [_P]),
     "ircur_destroy": (None, [_P]),
     "ircur_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ircur_last_error": (ctypes.c_char_p, [_P]),
@@ -342,3 +360,145 @@ class IRCUR:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ unrolled
+
+class IRCURUnrolled:
+    """A batch of independent instances for the unrolled, differentiable mode.
+
+    instances: list of (D, W*, V*, sI, sJ, seed) with D a CUDA tensor (float64
+    or float32, all the same dtype) and W*, V* its target factors (n1 x r,
+    n2 x r, same dtype).  K steps, rank r, gate width tau_rel.
+    """
+
+    def __init__(self, instances, r, K, tau_rel=0.05, stream=None):
+        import torch
+        if not instances:
+            raise ValueError("empty batch")
+        dt = instances[0][0].dtype
+        if dt not in (torch.float64, torch.float32):
+            raise ValueError("the unrolled mode takes float64 or float32 data")
+        self.dtype = F64 if dt == torch.float64 else F32
+        self.tdtype = dt
+        self.r, self.K, self.nb = r, K, len(instances)
+        self.stream = stream
+        self._keep = []
+        arr = (Instance * self.nb)()
+        self.shapes = []
+        for b, (D, Ws, Vs, sI, sJ, seed) in enumerate(instances):
+            if not (D.is_cuda and D.dim() == 2 and D.stride(1) == 1 and D.dtype == dt):
+                raise ValueError("every D must be a 2-D CUDA tensor of the batch dtype with unit column stride")
+            Ws = Ws.to(dt).contiguous()
+            Vs = Vs.to(dt).contiguous()
+            if Ws.shape != (D.shape[0], r) or Vs.shape != (D.shape[1], r):
+                raise ValueError("W* must be n1 x r and V* n2 x r")
+            self._keep += [D, Ws, Vs]
+            it = arr[b]
+            it.n1, it.n2 = D.shape
+            it.ldD = D.stride(0)
+            it.sI, it.sJ = sI, sJ
+            it.D = D.data_ptr()
+            it.Dt = None
+            it.ldDt = 0
+            it.Wstar, it.Vstar = Ws.data_ptr(), Vs.data_ptr()
+            it.seed = seed
+            self.shapes.append((D.shape[0], D.shape[1], sI, sJ))
+        h = ctypes.c_void_p()
+        rc = lib().ircur_unrolled_create(ctypes.byref(h), arr, self.nb, r, K, self.dtype, float(tau_rel),
+                                         _stream_handle(stream))
+        if rc != OK:
+            raise IrcurError(rc, "ircur_unrolled_create: " + strerror(rc))
+        self.h = h
+        self.device = instances[0][0].device
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise IrcurError(rc, f"{what}: {strerror(rc)}: {lib().ircur_unrolled_last_error(self.h).decode()}")
+        return rc
+
+    def forward(self, zeta):
+        """Losses (nb,) float64 for thresholds zeta (K,)."""
+        import torch
+        z = zeta.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        if z.shape != (self.K,):
+            raise ValueError(f"zeta must have shape ({self.K},)")
+        self._z = z
+        loss = torch.empty(self.nb, dtype=torch.float64, device=self.device)
+        self._check(lib().ircur_unrolled_forward(self.h, ctypes.c_void_p(z.data_ptr()),
+                                                 ctypes.c_void_p(loss.data_ptr())), "ircur_unrolled_forward")
+        return loss
+
+    def backward(self, dloss=None):
+        """d(sum_b dloss_b loss_b)/d zeta (K,) float64 for the last forward."""
+        import torch
+        dz = torch.empty(self.K, dtype=torch.float64, device=self.device)
+        w = None
+        if dloss is not None:
+            w = dloss.detach().to(device=self.device, dtype=torch.float64).contiguous()
+            self._w = w
+        self._check(lib().ircur_backward(self.h, None if w is None else ctypes.c_void_p(w.data_ptr()),
+                                         ctypes.c_void_p(dz.data_ptr())), "ircur_backward")
+        return dz
+
+    def factors(self, b, k):
+        import torch
+        n1, n2, _, _ = self.shapes[b]
+        At = torch.empty((self.r, n1), dtype=self.tdtype, device=self.device)
+        B = torch.empty((self.r, n2), dtype=self.tdtype, device=self.device)
+        self._check(lib().ircur_unrolled_get_factors(self.h, b, k, ctypes.c_void_p(At.data_ptr()),
+                                                     ctypes.c_void_p(B.data_ptr())), "ircur_unrolled_get_factors")
+        (torch.cuda.current_stream() if self.stream is None else self.stream).synchronize()
+        return At, B
+
+    def sets(self, b, k):
+        _, _, sI, sJ = self.shapes[b]
+        I = np.zeros(sI, np.int32)
+        J = np.zeros(sJ, np.int32)
+        self._check(lib().ircur_unrolled_get_sets(self.h, b, k, I.ctypes.data_as(_I32P), J.ctypes.data_as(_I32P)),
+                    "ircur_unrolled_get_sets")
+        return I, J
+
+    def status(self):
+        f = np.zeros(self.nb, np.int32)
+        self._check(lib().ircur_unrolled_status(self.h, f.ctypes.data_as(_I32P)), "ircur_unrolled_status")
+        return f
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ircur_unrolled_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd_function():
+    import torch
+
+    class UnrolledLoss(torch.autograd.Function):
+        """loss = sum_b loss_b(zeta) of an IRCURUnrolled batch; backward is the
+        library's adjoint (ircur_backward)."""
+
+        @staticmethod
+        def forward(ctx, zeta, batch):
+            losses = batch.forward(zeta)
+            ctx.batch = batch
+            ctx.zdtype = zeta.dtype
+            ctx.zdev = zeta.device
+            return losses.sum().to(device=zeta.device, dtype=zeta.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            dz = ctx.batch.backward(None).to(device=ctx.zdev)
+            return (dz * g.to(torch.float64)).to(ctx.zdtype), None
+
+    return UnrolledLoss
+
+
+def unrolled_loss(zeta, batch):
+    """Differentiable total loss of the batch as a function of zeta (K,)."""
+    return _autograd_function().apply(zeta, batch)

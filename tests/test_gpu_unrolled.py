@@ -1,0 +1,167 @@
+"""GPU parity of the unrolled, differentiable mode against the FP64 oracle.
+
+- forward: per-instance losses and final factors equal the oracle's
+  (hard threshold, tau_rel = 0, and gated) on a ragged batch;
+- backward: d loss / d zeta_k equals the oracle's adjoint (G3: <= 1e-9 in
+  FP64, <= 1e-4 in FP32);
+- G2 on the device: central finite differences of the GPU forward in zeta_k
+  agree with the GPU adjoint at n = 200 (FP64, gated);
+- the torch.autograd.Function wrapper returns the same gradient.
+"""
+import numpy as np
+import pytest
+
+from oracle import ircur as O
+from oracle import sampler
+from oracle import unrolled as U
+from paper_2010_07422_amd import synth
+from tests.gpu_util import require_gpu, to_dev, factors_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(ns=(200, 257, 300), r=5, alpha=0.1, seed0=11):
+    out = []
+    for q, n in enumerate(ns):
+        p = synth.planted(n, n, r, alpha, seed=seed0 + q)
+        s = synth.sample_size(4, r, n)
+        out.append((p, s, 100 + q))
+    return out
+
+
+def _gpu_batch(torch, items, r, K, tau, dtype):
+    from paper_2010_07422_amd.ircur import IRCURUnrolled
+    inst = []
+    for p, s, seed in items:
+        inst.append((to_dev(torch, p.D, dtype), to_dev(torch, p.W, dtype), to_dev(torch, p.V, dtype), s, s, seed))
+    return IRCURUnrolled(inst, r, K, tau_rel=tau)
+
+
+def _oracle(items, r, zetas, tau, f32=False):
+    losses, grads = [], []
+    for p, s, seed in items:
+        n1, n2 = p.D.shape
+        D = p.D.astype(np.float32).astype(np.float64) if f32 else p.D
+        W = p.W.astype(np.float32).astype(np.float64) if f32 else p.W
+        V = p.V.astype(np.float32).astype(np.float64) if f32 else p.V
+        IJ = [sampler.draw_IJ(seed, k, n1, n2, s, s) for k in range(len(zetas))]
+        ell, g, tape = U.loss_and_grad(D, IJ, zetas, r, tau, W, V)
+        losses.append(ell)
+        grads.append(g.zeta)
+    return np.array(losses), np.sum(grads, axis=0), tape
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.05])
+def test_forward_matches_oracle_f64(tau):
+    torch = require_gpu()
+    items = _batch()
+    r, K = 5, 6
+    zetas = 0.7 ** np.arange(K) * np.mean([p.Lmax for p, _, _ in items])
+    print(f"case unrolled forward f64 tau={tau}", flush=True)
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float64)
+    loss = ub.forward(torch.tensor(zetas)).cpu().numpy()
+    ref, _, _ = _oracle(items, r, zetas, tau)
+    print("loss", loss, ref, flush=True)
+    assert np.allclose(loss, ref, rtol=1e-9, atol=0)
+    # final factors of every instance
+    for b, (p, s, seed) in enumerate(items):
+        n1, n2 = p.D.shape
+        IJ = [sampler.draw_IJ(seed, k, n1, n2, s, s) for k in range(K)]
+        I0, J0 = ub.sets(b, 0)
+        assert np.array_equal(I0, IJ[0][0]) and np.array_equal(J0, IJ[0][1])
+        tape = U.forward(p.D, IJ, zetas, r, tau)
+        At, B = ub.factors(b, K)
+        A = At.cpu().numpy().T
+        d = O.factored_rel_diff(A, B.cpu().numpy(), tape.A[-1], tape.B[-1])
+        assert d <= 1e-10, (b, d)
+    assert not np.any(ub.status() & 16)
+    ub.close()
+
+
+def test_backward_matches_oracle_f64():
+    torch = require_gpu()
+    items = _batch()
+    r, K, tau = 5, 6, 0.05
+    zetas = 0.7 ** np.arange(K) * np.mean([p.Lmax for p, _, _ in items])
+    print("case unrolled backward f64", flush=True)
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float64)
+    ub.forward(torch.tensor(zetas))
+    dz = ub.backward().cpu().numpy()
+    flags = ub.status()
+    _, ref, _ = _oracle(items, r, zetas, tau)
+    err = np.abs(dz - ref).max() / np.abs(ref).max()
+    print("dzeta", dz, ref, "err", err, "flags", flags, flush=True)
+    assert err <= 1e-9
+    assert not np.any(flags & 1)
+    ub.close()
+
+
+def test_backward_hard_threshold_has_no_zeta_gradient():
+    torch = require_gpu()
+    items = _batch(ns=(200,))
+    r, K = 5, 4
+    zetas = 0.7 ** np.arange(K) * items[0][0].Lmax
+    ub = _gpu_batch(torch, items, r, K, 0.0, torch.float64)
+    ub.forward(torch.tensor(zetas))
+    dz = ub.backward().cpu().numpy()
+    assert np.all(dz == 0.0)
+    ub.close()
+
+
+def test_G2_central_differences_on_device():
+    torch = require_gpu()
+    items = _batch(ns=(200,))
+    r, K, tau = 5, 8, 0.05
+    zetas = 0.7 ** np.arange(K) * items[0][0].Lmax
+    print("case unrolled FD n=200", flush=True)
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float64)
+    ub.forward(torch.tensor(zetas))
+    dz = ub.backward().cpu().numpy()
+    fd = np.zeros(K)
+    for k in range(K):
+        h = 1e-5 * zetas[k]
+        zp, zm = zetas.copy(), zetas.copy()
+        zp[k] += h
+        zm[k] -= h
+        lp = float(ub.forward(torch.tensor(zp)).sum())
+        lm = float(ub.forward(torch.tensor(zm)).sum())
+        fd[k] = (lp - lm) / (zp[k] - zm[k])
+    err = np.abs(fd - dz).max() / np.abs(dz).max()
+    print("fd", fd, "adjoint", dz, "err", err, flush=True)
+    assert err <= 1e-6
+    ub.close()
+
+
+def test_f32_against_f64_oracle():
+    torch = require_gpu()
+    items = _batch(ns=(1000, 1500))
+    r, K, tau = 5, 10, 0.05
+    zetas = 0.7 ** np.arange(K) * np.mean([p.Lmax for p, _, _ in items])
+    print("case unrolled f32", flush=True)
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float32)
+    loss = ub.forward(torch.tensor(zetas)).cpu().numpy()
+    dz = ub.backward().cpu().numpy()
+    ref_l, ref_g, _ = _oracle(items, r, zetas, tau, f32=True)
+    lerr = np.abs(loss - ref_l).max() / np.abs(ref_l).max()
+    gerr = np.abs(dz - ref_g).max() / np.abs(ref_g).max()
+    print("f32 loss err", lerr, "grad err", gerr, flush=True)
+    assert lerr <= 1e-4 and gerr <= 1e-4
+    ub.close()
+
+
+def test_autograd_function():
+    torch = require_gpu()
+    from paper_2010_07422_amd.ircur import unrolled_loss
+    items = _batch(ns=(200, 220))
+    r, K, tau = 5, 5, 0.05
+    z0 = 0.7 ** np.arange(K) * np.mean([p.Lmax for p, _, _ in items])
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float64)
+    zeta = torch.tensor(z0, dtype=torch.float32, requires_grad=True)
+    loss = unrolled_loss(zeta, ub)
+    loss.backward()
+    ub2 = _gpu_batch(torch, items, r, K, tau, torch.float64)
+    ub2.forward(zeta.detach())
+    dz = ub2.backward().cpu().numpy()
+    assert np.allclose(zeta.grad.numpy(), dz.astype(np.float32), rtol=1e-6, atol=0)
+    ub.close()
+    ub2.close()
