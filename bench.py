@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -71,17 +73,86 @@ def run_gpu(D, p, r, s, steps, warmup, label):
     return out, At.double().cpu().numpy().T, B.double().cpu().numpy()
 
 
+def unrolled_items(nb=32, r=5, K=10, seed=7):
+    """The unrolled workload: nb planted instances, n ~ U{1000..3000},
+    alpha ~ U[0.1, 0.3], r = 5, |I| = |J| = ceil(20 ln n), K = 10 steps."""
+    from paper_2010_07422_amd import synth
+    batch = synth.unrolled_batch(nb=nb, r=r, seed=seed)
+    zeta = 0.7 ** np.arange(K) * float(np.mean([it.inst.Lmax for it in batch]))
+    return batch, zeta
+
+
+def run_unrolled(batch, zeta, r, K, tau, steps, warmup):
+    """One step = forward (K gated IRCUR iterations over the batch + loss) and
+    backward (adjoint in zeta) of the whole batch, FP32 data and factors."""
+    import torch
+    from paper_2010_07422_amd.ircur import IRCURUnrolled
+    inst = []
+    for b, it in enumerate(batch):
+        p = it.inst
+        inst.append((torch.tensor(p.D, dtype=torch.float32, device="cuda"),
+                     torch.tensor(p.W, dtype=torch.float32, device="cuda"),
+                     torch.tensor(p.V, dtype=torch.float32, device="cuda"), it.s, it.s, 1000 + b))
+    ub = IRCURUnrolled(inst, r, K, tau_rel=tau)
+    z = torch.tensor(zeta, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        ub.forward(z)
+        ub.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = ub.forward(z)
+        dz = ub.backward()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        ub.forward(z)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t1
+    flags = ub.status()
+    out = {"steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps, "forward_ms": 1e3 * tf / steps,
+           "loss_sum": float(loss.sum()), "dzeta": [float(v) for v in dz.cpu()],
+           "flags_any": int(np.bitwise_or.reduce(flags))}
+    ub.close()
+    return out
+
+
+def unrolled_cpu_baseline(batch, zeta, r, tau, budget_s=15.0):
+    """The FP64 oracle's forward + adjoint on the first instances of the same
+    batch until `budget_s` is spent, scaled to whole-batch steps/s."""
+    from oracle import sampler
+    from oracle import unrolled as U
+    t0 = time.perf_counter()
+    done = 0
+    for b, it in enumerate(batch):
+        p = it.inst
+        IJ = [sampler.draw_IJ(1000 + b, k, it.n, it.n, it.s, it.s) for k in range(len(zeta))]
+        U.loss_and_grad(p.D, IJ, zeta, r, tau, p.W, p.V)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t = time.perf_counter() - t0
+    return {"value": (done / t) / len(batch), "unit": "steps/s", "cores": _threads(), "kind": "oracle",
+            "sample": f"forward + adjoint of the first {done} of {len(batch)} instances (FP64 NumPy), "
+                      f"{t:.1f} s, scaled to the whole batch"}
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count()
+
+
 def cpu_baseline(p, r, s, budget_s=15.0):
     """The FP64 oracle timed on the host on a bounded sample: the first
     iterations of the same IRCUR-R run, stopped once `budget_s` is spent."""
-    import numpy as np
     from oracle import ircur as O
     from oracle import sampler
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
+    threads = _threads()
     n = p.D.shape[0]
     A = np.zeros((n, r))
     B = np.zeros((r, n))
@@ -106,6 +177,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--unrolled-steps", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of 256 MiB five times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -171,6 +244,13 @@ def main():
         "kernel_us": {k: round(v, 3) for k, v in res["kernel_us"].items()},
         "extra": extra,
     }
+    if not args.no_unrolled:
+        ubatch, uzeta = unrolled_items()
+        ur = run_unrolled(ubatch, uzeta, 5, 10, 0.05, args.unrolled_steps, 3)
+        line["unrolled"] = {"metric": "unrolled forward+backward steps/s (32 instances, n in [1000, 3000], "
+                                      "r=5, K=10, tau_rel=0.05, FP32)", **ur}
+        if not args.no_cpu:
+            line["unrolled"]["cpu_baseline"] = unrolled_cpu_baseline(ubatch, uzeta, 5, 0.05, args.cpu_budget)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, r, s, args.cpu_budget)
     print(json.dumps(line), flush=True)
