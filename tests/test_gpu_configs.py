@@ -1,0 +1,214 @@
+"""GPU runs of the named workloads and edge cases, through the C ABI.
+
+- n = 3000, r = 5, FP32: to e <= 1e-5 against the FP64 oracle on the same
+  (float-rounded) D and index sets, <= 1e-5;
+- n = 10^4, r = 10, D in BF16: against an FP64 GPU run on the same D, for L
+  (factored difference) and S (sampled blocks), <= 1e-2; reaches e <= 1e-5;
+- 76800 x 1200 video stand-in, r = 2, |I| = 800, |J| = 200, FP32: against the
+  FP64 oracle at the final iteration, <= 1e-5, and sampled entries of L;
+- edge cases: |I| = n1 and |J| = n2 (CUR of the whole matrix), r = 1,
+  zeta_0 = 0, exact low rank, a NaN in D, resume from a checkpoint, IRCUR-F,
+  err_mode 1, bitwise repeatability.
+"""
+import numpy as np
+import pytest
+
+from oracle import ircur as O
+from oracle import sampler
+from paper_2010_07422_amd import synth
+from tests.gpu_util import require_gpu, to_dev, factors_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(torch, D, dtype, r, sI, sJ, zeta0, **kw):
+    from paper_2010_07422_amd.ircur import IRCUR
+    Dd = to_dev(torch, D, dtype) if not hasattr(D, "is_cuda") else D
+    return IRCUR(Dd, r, sI, sJ, zeta0, **kw), Dd
+
+
+def test_planted_n3000_r5_f32_against_oracle():
+    torch = require_gpu()
+    cfg = synth.CONFIGS["planted_n3000_r5_f32"]
+    n, r = cfg["n"], cfg["r"]
+    p = synth.planted(n, n, r, cfg["alpha"], seed=cfg["data_seed"])
+    s = synth.sample_size(cfg["c"], r, n)
+    D32 = p.D.astype(np.float32)
+    print("case n=3000 r=5 f32", flush=True)
+    ctx, _ = _ctx(torch, D32, torch.float32, r, s, s, p.Lmax, gamma=cfg["gamma"], eps=cfg["eps"],
+                  max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
+    it, e, rc = ctx.solve()
+    A, B = factors_np(ctx)
+    ref = O.ircur(D32.astype(np.float64), r, s, s, p.Lmax, cfg["gamma"], 0.0, it, seed=cfg["index_seed"],
+                  resample=True)
+    d = O.factored_rel_diff(A, B, ref.A, ref.B)
+    print("iters", it, "e", e, "diff vs oracle", d, "vs truth", O.factored_rel_diff(A, B, p.W, p.V.T), flush=True)
+    assert e <= 1e-5 and d <= 1e-5
+    ctx.close()
+
+
+def test_planted_n10000_r10_bf16_against_f64_gpu():
+    torch = require_gpu()
+    cfg = synth.CONFIGS["planted_n10000_r10_bf16"]
+    n, r = cfg["n"], cfg["r"]
+    p = synth.planted(n, n, r, cfg["alpha"], seed=cfg["data_seed"])
+    s = synth.sample_size(cfg["c"], r, n)
+    print("case n=10000 r=10 bf16 vs f64", flush=True)
+    D64 = to_dev(torch, p.D, torch.float64)
+    out = {}
+    for name, D in (("bf16", D64.to(torch.bfloat16)), ("f64", D64)):
+        ctx, _ = _ctx(torch, D, None, r, s, s, p.Lmax, gamma=cfg["gamma"], eps=cfg["eps"],
+                      max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
+        it, e, rc = ctx.solve()
+        A, B = factors_np(ctx)
+        cur = ctx.cur()
+        out[name] = (A, B, it, e, cur["S_I"].double().cpu().numpy(), cur["I"])
+        ctx.close()
+        del D
+    A1, B1, it1, e1, S1, I1 = out["bf16"]
+    A0, B0, it0, e0, S0, I0 = out["f64"]
+    dL = O.factored_rel_diff(A1, B1, A0, B0)
+    print("bf16 iters", it1, "e", e1, "f64 iters", it0, "e", e0, "L diff", dL, flush=True)
+    assert e1 <= 1e-5 and e0 <= 1e-5
+    assert dL <= 1e-2
+    # S on the sampled rows of the bf16 run's last iteration, against the FP64
+    # estimate thresholded on the same rows
+    Dh = p.D[I1, :]
+    S_ref = O.hard_threshold(Dh - A0[I1, :] @ B0, cfg_zeta(p, cfg, it1))
+    dS = np.linalg.norm(S1 - S_ref) / np.linalg.norm(S_ref)
+    print("S diff", dS, flush=True)
+    assert dS <= 1e-2
+
+
+def cfg_zeta(p, cfg, it):
+    return p.Lmax * cfg["gamma"] ** (it - 1)
+
+
+def test_video_76800x1200_f32():
+    torch = require_gpu()
+    cfg = synth.CONFIGS["video_76800x1200_r2_f32"]
+    v = synth.video(cfg["h"], cfg["w"], cfg["frames"], seed=cfg["data_seed"])
+    Lmax = float(np.abs(v.F @ v.G.T).max())
+    r, sI, sJ = cfg["r"], cfg["sI"], cfg["sJ"]
+    print("case video 76800x1200", flush=True)
+    ctx, Dd = _ctx(torch, v.D, torch.float32, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=cfg["eps"],
+                   max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
+    it, e, rc = ctx.solve()
+    A, B = factors_np(ctx)
+    # the oracle's last iteration from the GPU's previous factors (a full
+    # oracle run at this size takes minutes): one step, same sets
+    ctx2, _ = _ctx(torch, Dd, None, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=-1.0, max_iter=it,
+                   seed=cfg["index_seed"], resample=True)
+    ctx2.enqueue(it - 1)
+    ctx2.sync()
+    Ap, Bp = factors_np(ctx2)
+    ctx2.close()
+    I, J = sampler.draw_IJ(cfg["index_seed"], it - 1, v.D.shape[0], v.D.shape[1], sI, sJ)
+    D64 = v.D.astype(np.float64)
+    ref = O.step(D64, Ap, Bp, I, J, Lmax * cfg["gamma"] ** (it - 1), r)
+    d = O.factored_rel_diff(A, B, ref["A1"], ref["B1"])
+    truth = O.factored_rel_diff(A, B, v.F, v.G.T)
+    print("iters", it, "e", e, "last step vs oracle", d, "vs background", truth, flush=True)
+    assert e <= 1e-5
+    assert d <= 1e-5
+    # sampled entries of L against the oracle's product
+    rng = np.random.default_rng(0)
+    ii = rng.integers(0, v.D.shape[0], 2000)
+    jj = rng.integers(0, v.D.shape[1], 2000)
+    Lg = np.einsum("ij,ji->i", A[ii, :], B[:, jj])
+    Lo = np.einsum("ij,ji->i", ref["A1"][ii, :], ref["B1"][:, jj])
+    assert np.max(np.abs(Lg - Lo)) <= 1e-4 * np.abs(Lo).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["full_sets", "rank1", "zeta0_zero", "exact_rank"])
+def test_edge_cases_f64(case):
+    torch = require_gpu()
+    print("case edge", case, flush=True)
+    if case == "full_sets":
+        p = synth.planted(60, 50, 3, 0.05, seed=3)
+        D, r, sI, sJ, z0, iters = p.D, 3, 60, 50, p.Lmax, 6
+    elif case == "rank1":
+        p = synth.planted(300, 280, 1, 0.1, seed=4)
+        D, r, sI, sJ, z0, iters = p.D, 1, 40, 37, p.Lmax, 8
+    elif case == "zeta0_zero":
+        p = synth.planted(200, 200, 2, 0.1, seed=5)
+        D, r, sI, sJ, z0, iters = p.D, 2, 30, 30, 0.0, 3
+    else:
+        D, _, _ = synth.exact_lowrank(250, 240, 4, seed=6)
+        r, sI, sJ, z0, iters = 4, 40, 40, float(np.abs(D).max()), 3
+    ctx, _ = _ctx(torch, D, torch.float64, r, sI, sJ, z0, eps=-1.0, max_iter=iters, seed=9, resample=True)
+    ctx.solve()
+    A, B = factors_np(ctx)
+    ref = O.ircur(D, r, sI, sJ, z0, 0.7, -1.0, iters, seed=9, resample=True)
+    if case == "zeta0_zero":
+        assert np.all(A == 0.0) and np.all(B == 0.0)      # S = D on the blocks: M = 0, U^+ = 0
+        assert np.abs(ref.A @ ref.B).max() == 0.0
+    else:
+        d = O.factored_rel_diff(A, B, ref.A, ref.B)
+        print("diff", d, flush=True)
+        assert d <= 1e-10
+    if case == "exact_rank":
+        assert O.factored_rel_diff(A, B, D, np.eye(D.shape[1])) <= 1e-13    # Theorem 1
+    ctx.close()
+
+
+def test_nonfinite_input_is_reported():
+    torch = require_gpu()
+    from paper_2010_07422_amd.ircur import IrcurError, ERR_NONFINITE
+    p = synth.planted(200, 200, 2, 0.1, seed=5)
+    D = p.D.copy()
+    I, J = sampler.draw_IJ(1, 0, 200, 200, 30, 30)
+    D[I[3], 17] = np.nan
+    ctx, _ = _ctx(torch, D, torch.float64, 2, 30, 30, p.Lmax, eps=-1.0, max_iter=5, seed=1)
+    with pytest.raises(IrcurError) as ei:
+        ctx.solve()
+    assert ei.value.code == ERR_NONFINITE
+    ctx.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    torch = require_gpu()
+    p = synth.planted(800, 700, 4, 0.1, seed=8)
+    kw = dict(eps=-1.0, max_iter=20, seed=3, resample=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float32, 4, 90, 80, p.Lmax, **kw)
+    ctx.enqueue(8)
+    ctx.sync()
+    blob = ctx.get_state()
+    ctx.enqueue(12)
+    ctx.sync()
+    A1, B1 = factors_np(ctx)
+    h1 = ctx.history()
+    ctx2, _ = _ctx(torch, Dd, None, 4, 90, 80, p.Lmax, **kw)
+    ctx2.set_state(blob)
+    ctx2.enqueue(12)
+    ctx2.sync()
+    A2, B2 = factors_np(ctx2)
+    assert np.array_equal(A1, A2) and np.array_equal(B1, B2)
+    assert h1 == ctx2.history()
+    ctx.close()
+    ctx2.close()
+
+
+def test_repeat_is_bitwise_and_modes():
+    torch = require_gpu()
+    p = synth.planted(600, 650, 3, 0.1, seed=12)
+    res = []
+    for rep in range(2):
+        ctx, _ = _ctx(torch, p.D, torch.float64, 3, 70, 75, p.Lmax, eps=-1.0, max_iter=12, seed=4, resample=False)
+        ctx.solve()
+        res.append(factors_np(ctx) + (ctx.history(),))
+        ctx.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+    # IRCUR-F against the oracle
+    ref = O.ircur(p.D, 3, 70, 75, p.Lmax, 0.7, -1.0, 12, seed=4, resample=False)
+    assert O.factored_rel_diff(res[0][0], res[0][1], ref.A, ref.B) <= 1e-10
+    assert np.allclose(res[0][2], ref.e_hist, rtol=1e-6)
+    # err_mode 1 (the below-threshold part of D - L_k) against the oracle
+    ctx, _ = _ctx(torch, p.D, torch.float64, 3, 70, 75, p.Lmax, eps=-1.0, max_iter=6, seed=4, resample=True,
+                  err_mode=1)
+    ctx.solve()
+    ref = O.ircur(p.D, 3, 70, 75, p.Lmax, 0.7, -1.0, 6, seed=4, resample=True, err_mode=1)
+    assert np.allclose(ctx.history(), ref.e_hist, rtol=1e-6)
+    ctx.close()
