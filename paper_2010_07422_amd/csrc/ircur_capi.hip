@@ -118,6 +118,11 @@ struct ircur_ctx {
     void* GmJ = nullptr;
     void* scaleJ = nullptr;
     double* TAd = nullptr;
+    double* Abc = nullptr;          // compact A_k[I, :] (sI16 x 16), written by the core kernel
+    double* Bsc = nullptr;          // compact B_k[:, J] (16 x sJ16)
+    double* Zr = nullptr;           // reduced Z of the SVD (sJ16 x 16)
+    double* rp = nullptr;           // SVD residual parts (G)
+    bool lds_svd = false;           // the SVD keeps its block of M in LDS (P = 16)
     int32_t* Icur = nullptr;        // index sets of an export (device)
     int32_t* Jcur = nullptr;
     unsigned long long* nnz = nullptr;
@@ -217,7 +222,7 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
-                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->st,
+                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->st,
                     c->info, c->hist};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -307,7 +312,9 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     CoreArgs ca{};
     ca.D = c->D; ca.ldD = p.ldD; ca.I = Id; ca.J = Jd; ca.sI = p.sI; ca.sJ = p.sJ;
     ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
-    ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.MA = c->MA; ca.MB = c->MB; ca.st = c->st;
+    ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.MA = c->MA; ca.st = c->st;
+    ca.MB = c->lds_svd ? nullptr : c->MB;
+    ca.Abc = c->Abc; ca.Bsc = c->Bsc;
     HIPCHK(c, launch_core(ca, p.dtype, c->R, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][1], s));
 
@@ -329,7 +336,13 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.TAd = c->TAd;
     sa.qs = row_stride(c->R, (int)c->fsz);
     sa.info = c->info + k; sa.st = c->st;
-    HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
+    sa.Abc = c->Abc; sa.Bsc = c->Bsc; sa.Zr = c->Zr; sa.rp = c->rp;
+    if (c->lds_svd) {
+        sa.warm = (sa.warm & 0xff) | ((p.dtype == IRCUR_F64 ? 0 : 1) << 8);
+        HIPCHK(c, launch_svdl(sa, c->svd_lds, s));
+    } else {
+        HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
+    }
     c->have_prevV = true;
     c->lastJ.assign(Jhost, Jhost + p.sJ);
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
@@ -459,8 +472,18 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     int pb = P;
     size_t lds = 0;
     {
+        // P = 16: the variant with the row block of M in LDS (fewest workgroups
+        // of 8, 16, 32 that fit); otherwise, or if none fits, the streaming one.
         bool ok = false;
+        if (P == 16) {
+            for (int g : {8, 16, 32}) {
+                const int bs = 16 * ((p.sI + 16 * g - 1) / (16 * g));
+                const size_t l = svdl_lds_bytes(p.sJ, bs, g);
+                if (l <= 160 * 1024) { c->G = g; c->bs = bs; lds = l; ok = true; c->lds_svd = true; break; }
+            }
+        }
         for (int g : {8, 16, 32}) {
+            if (ok) break;
             c->G = g;
             c->bs = 16 * ((p.sI + 16 * g - 1) / (16 * g));   // rows per workgroup, multiple of 16
             lds = svd_lds_bytes(p.sJ, c->bs, P);
@@ -515,7 +538,18 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         HIPCHK(c, hipMemset(c->MA, 0, sI16 * sJ16 * sizeof(double)));
         HIPCHK(c, hipMemset(c->MB, 0, sI16 * sJ16 * sizeof(double)));
     }
-    TRY(dalloc(c, &c->Zp, (size_t)c->G * p.sJ * c->psvd));
+    {
+        const size_t sI16 = ((size_t)p.sI + 15) / 16 * 16, sJ16 = ((size_t)p.sJ + 15) / 16 * 16;
+        TRY(dalloc(c, &c->Zp, (size_t)c->G * sJ16 * c->psvd));
+        if (c->lds_svd) {
+            TRY(dalloc(c, &c->Abc, sI16 * 16));
+            TRY(dalloc(c, &c->Bsc, 16 * sJ16));
+            TRY(dalloc(c, &c->Zr, sJ16 * 16));
+            TRY(dalloc(c, &c->rp, (size_t)c->G));
+            HIPCHK(c, hipMemset(c->Abc, 0, sI16 * 16 * sizeof(double)));
+            HIPCHK(c, hipMemset(c->Bsc, 0, 16 * sJ16 * sizeof(double)));
+        }
+    }
     TRY(dalloc(c, &c->Gp, (size_t)c->G * 2 * c->psvd * c->psvd));
     TRY(dalloc(c, &c->prevV, (size_t)p.sJ * R));
     TRY(dalloc(c, &c->W, (size_t)p.sI * R));

@@ -78,15 +78,16 @@ __device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
 // 16-byte loads (all rows at once unless they exceed the LDS budget) and reads
 // it back as broadcast loads.  The index arrays carry kIndexPad valid trailing
 // entries, so a group may read past the end of a wave's rows.
-template <typename T> struct RowsInFlight { static constexpr int value = 8; };
-template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
-template <> struct RowsInFlight<double> { static constexpr int value = 4; };
+template <typename T> struct RowsInFlight { static constexpr int value = 32; };
+template <> struct RowsInFlight<bf16_t> { static constexpr int value = 64; };
+template <> struct RowsInFlight<double> { static constexpr int value = 16; };
 
 template <typename T, typename F, int R, bool LIT, bool GATE = false>
 __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta, float zeta_f,
                                           F (*red)[R][64], double (*redz)[64], double (*redd)[64],
                                           F* qstage, int segmax, F tauz = F(0)) {
     constexpr int U = RowsInFlight<T>::value;
+    static_assert(U <= kIndexPad, "the row read-ahead must stay inside the index padding");
     constexpr int QS = RowStride<F, R>::value;
     constexpr int UPR = QS * (int)sizeof(F) / 16;          // 16-byte units per row
     const int lane = threadIdx.x & 63;

@@ -11,8 +11,9 @@ namespace ircur {
 // smallest entry >= r with the extra factor rows held at zero.
 constexpr int kRanks[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
 // Trailing entries after every stored index set (copies of its last index):
-// the pass kernel reads up to this many indices past the rows it uses.
-constexpr int kIndexPad = 16;
+// the pass kernel reads up to RowsInFlight - 1 (<= 63) indices past the rows
+// a wave uses, so the padding must be at least the largest RowsInFlight.
+constexpr int kIndexPad = 64;
 
 // Row stride (elements) of the per-row data of the pass: 3R rounded up to a
 // multiple of 16 bytes.
@@ -94,7 +95,12 @@ struct CoreArgs {
     //   MB block (tj, ks), tj < sJ16/16, ks < sI16/4:  lane l holds
     //      M[4 ks + l/16][16 tj + l%16]            (A operand of M^T Y)
     double* MA;
-    double* MB;
+    double* MB;            // nullptr when the SVD does not read it
+    // Compact copies of the sampled factor rows/columns for the SVD (doubles,
+    // zero padded, nullptr if not needed): Abc[a * 16 + c] = A_k[I_a, c]
+    // (sI16 x 16), Bsc[c * sJ16 + b] = B_k[c, J_b] (16 x sJ16).
+    double* Abc;
+    double* Bsc;
     DevState* st;
 };
 
@@ -129,6 +135,12 @@ struct SvdArgs {
     double* TAd;           // R x R: Ly^-T in double (for U^+ on export)
     SvdInfo* info;         // one record (this iteration)
     DevState* st;
+    // LDS-resident variant (P = 16): compact factor copies written by the
+    // core kernel, the reduced Z (sJ16 x 16) and per-workgroup residual parts
+    const double* Abc;     // sI16 x 16
+    const double* Bsc;     // 16 x sJ16
+    double* Zr;            // sJ16 x 16
+    double* rp;            // G
 };
 
 struct FinArgs {
@@ -236,10 +248,15 @@ hipError_t launch_core(const CoreArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s);
 // Batch of nb cores, arr_dev[b] per core (device array); G in {1, 2, 4, 8}, P = 16.
 hipError_t launch_svd_batch(const SvdArgs* arr_dev, int nb, int G, int P, size_t lds_bytes, hipStream_t s);
+// LDS-resident variant (P = 16): one core (G in {8, 16, 32}) or a batch (G in {2, 4, 8}).
+hipError_t launch_svdl(const SvdArgs& a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_svdl_batch(const SvdArgs* arr_dev, int nb, int G, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
 size_t svd_lds_bytes(int sJ, int bs16, int P);
+// LDS bytes of the variant that keeps its row block of M in LDS (P = 16).
+size_t svdl_lds_bytes(int sJ, int bs16, int G);
 hipError_t launch_cur(const CurArgs& a, int dtype, int R, hipStream_t s);
 hipError_t launch_upinv(const double* V, const double* TA, const double* W, int sI, int sJ, int R,
                         void* out, int dtype, hipStream_t s);

@@ -90,7 +90,15 @@ __global__ __launch_bounds__(256) void core_kernel(CoreArgs a) {
     a.M[idx] = mv;
     const int sJ16 = ((a.sJ + 15) / 16) * 16, sI16 = ((a.sI + 15) / 16) * 16;
     a.MA[((size_t)(ai >> 4) * (sJ16 >> 2) + (bj >> 2)) * 64 + ((bj & 3) << 4) + (ai & 15)] = mv;
-    a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
+    if (a.MB) a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
+    if (a.Abc && bj == 0) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) a.Abc[(size_t)ai * 16 + c] = (double)At[c * a.n1 + i];
+    }
+    if (a.Bsc && ai == 0) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) a.Bsc[(size_t)c * sJ16 + bj] = (double)B[c * a.n2 + j];
+    }
 }
 
 // ----------------------------------------------------------------- pass ---

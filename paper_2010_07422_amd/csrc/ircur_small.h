@@ -207,13 +207,16 @@ __device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, do
 
 // Orthonormalise the first `live` columns of X (m16 x P, LDS, row stride P)
 // in place by Cholesky QR (X <- X Linv^T with X^T X = L L^T), repeated while
-// max |X^T X - I| exceeds 1e-13 (at most three passes).  A dependent column
+// max |X^T X - I| exceeds 1e-13 (at most `passes` passes, 4 once a column
+// had to be refilled).  A dependent column
 // is refilled with pseudo-random entries and the pass repeated; columns at or
 // past `live` stay zero.
 template <int P>
 __device__ void orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
-                               double* Li, int* dead, double* scratch, double* red, uint64_t salt) {
-    for (int pass = 0; pass < 4; ++pass) {
+                               double* Li, int* dead, double* scratch, double* red, uint64_t salt,
+                               int passes = 4) {
+    int maxp = passes;
+    for (int pass = 0; pass < maxp; ++pass) {
         mm_small<P, true, false>(X, P, X, P, Gs, m16, scratch);
         // orthonormality defect
         double dev = 0.0;
@@ -233,6 +236,7 @@ __device__ void orthonormalise(double* X, int m16, int rows_valid, int live, dou
         int nd = 0;
         for (int j = 0; j < live; ++j) nd += dead[j];
         if (nd > 0) {
+            maxp = 4;   // a refilled column needs a further pass
             for (int e = threadIdx.x; e < rows_valid * P; e += NT) {
                 const int c = e % P;
                 if (c < live && dead[c]) X[e] = rnd_unit(salt ^ (0x5bd1e995ull * (uint64_t)(pass + 1)), (uint64_t)e);

@@ -433,6 +433,304 @@ __global__ __launch_bounds__(256) void svd_batch_kernel(const SvdArgs* __restric
     svd_body<G, P>(a, blockIdx.x);
 }
 
+
+// ---------------------------------------------------------------------------
+// Variant with the workgroup's row block of M resident in LDS (P = 16).
+//
+// Per subspace iteration each workgroup forms Y_blk = M_blk Q and the partial
+// Z_g = M_blk^T Y_blk from LDS, then exchanges through global memory in two
+// steps: after the first grid barrier it reduces only its slice of the rows
+// of Z (reduce-scatter), with the small Gram matrices reduced in full; after
+// the second it reads the residual parts of every slice and, if not
+// converged, the whole reduced Z (all-gather) for Q <- orth(Z).  The sampled
+// factor rows and columns come from compact copies written by the core
+// kernel; the warm start is orthonormalised in a single Cholesky-QR pass.
+size_t svdl_lds_bytes(int sJ, int bs16, int G) {
+    constexpr size_t P = 16;
+    const size_t sJ16 = ((size_t)sJ + 15) / 16 * 16;
+    const size_t ntj = sJ16 / 16;
+    const size_t tpg = (ntj + G - 1) / G;
+    size_t d = 0;
+    d += (size_t)bs16 * sJ16;         // M block
+    d += sJ16 * P;                    // Q
+    d += 3 * (size_t)bs16 * P;        // Y, Ab, Wb
+    d += 8 * P * P;                   // Gy, H, Gs, Ls, Li, Gam, Gam2, TA
+    d += 4 * P * P;                   // MFMA scratch
+    d += 64;                          // reduction buffer
+    d += tpg * 16 * P;                // this workgroup's slice of Z
+    return d * sizeof(double) + 64 * sizeof(int);
+}
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int G>
+__device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
+    constexpr int P = 16;
+    if (a.st->stop) return;
+#ifdef IRCUR_PHASE_PROFILE
+    uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
+#endif
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const int sI = a.sI, sJ = a.sJ, r = a.r, R = a.R;
+    const int bs16 = a.bs;
+    const int sJ16 = ((sJ + 15) / 16) * 16;
+    const int KSA = sJ16 / 4;
+    const int a0 = wg * bs16;
+    int nb = sI - a0;
+    if (nb > bs16) nb = bs16;
+    if (nb < 0) nb = 0;
+    const int nt_rows = (nb + 15) / 16;
+    const int ntj = sJ16 / 16;
+    const int tpg = (ntj + G - 1) / G;
+    const int z0 = min(wg * tpg, ntj) * 16;
+    const int z1 = min(min((wg + 1) * tpg, ntj) * 16, sJ);
+    const int zn = z1 > z0 ? z1 - z0 : 0;
+    const int fd = (a.warm >> 8) & 1;
+    const int warm = a.warm & 0xff;
+    const int l64 = tid & 63, w4 = tid >> 6;
+
+    double* Mb = smem;                          // bs16 x sJ16, row-tiled (MA) order
+    double* Q = Mb + (size_t)bs16 * sJ16;
+    double* Y = Q + (size_t)sJ16 * P;
+    double* Ab = Y + (size_t)bs16 * P;
+    double* Wb = Ab + (size_t)bs16 * P;
+    double* Gy = Wb + (size_t)bs16 * P;
+    double* H = Gy + P * P;                     // follows Gy (reduced together)
+    double* Gs = H + P * P;
+    double* Ls = Gs + P * P;
+    double* Li = Ls + P * P;
+    double* Gam = Li + P * P;
+    double* Gam2 = Gam + P * P;
+    double* TA = Gam2 + P * P;
+    double* scr = TA + P * P;
+    double* red = scr + 4 * P * P;
+    double* Zs = red + 64;                      // tpg*16 x P
+    int* dead = (int*)(Zs + (size_t)tpg * 16 * P);
+    double* Zp_all = a.Zp;                      // G x sJ16 x P
+    uint32_t nbar = 0;
+
+    // ---- stage: M block, A_k[I_blk, :], warm start ------------------------
+    {
+        const double* __restrict__ src = a.MA + (size_t)(a0 / 16) * KSA * 64;
+        const int have = nt_rows * KSA * 64;
+        // 16-byte loads, up to 20 per thread in flight (one round trip for
+        // blocks up to 80 KiB)
+        const dbl2* __restrict__ src2 = (const dbl2*)src;
+        dbl2* dst2 = (dbl2*)Mb;
+        const int have2 = have / 2, tot2 = bs16 * sJ16 / 2;
+        constexpr int V = 20;
+        for (int base = tid; base < tot2; base += NT * V) {
+            dbl2 v[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int e = base + u * NT;
+                v[u] = e < have2 ? src2[e] : dbl2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int e = base + u * NT;
+                if (e < tot2) dst2[e] = v[u];
+            }
+        }
+    }
+    for (int e = tid; e < bs16 * P; e += NT) {
+        const int ar = e / P;
+        Ab[e] = ar < nb ? a.Abc[(size_t)(a0 + ar) * P + (e - ar * P)] : 0.0;
+    }
+    for (int e = tid; e < sJ16 * P; e += NT) {
+        const int b = e / P, c = e - b * P;
+        double v = 0.0;
+        if (b < sJ && c < r) {
+            if (warm == 1) v = a.prevV[b * R + c];
+            else if (warm == 2) v = a.Bsc[(size_t)c * sJ16 + b];
+            else v = rnd_unit(a.salt, (uint64_t)e);
+        }
+        Q[e] = v;
+    }
+    __syncthreads();
+    PHASE(0);
+    if (warm == 2) orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red, a.salt + 17, 1);
+    else if (warm == 0) orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red, a.salt + 17);
+    __syncthreads();
+    PHASE(1);
+
+    int it = 0;
+    bool conv = false;
+    double rho = 0.0;
+    for (;;) {
+        // Y_blk = M_blk Q
+        for (int t = w4; t < bs16 / 16; t += 4) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+            if (t < nt_rows) {
+                const double* ma = Mb + (size_t)t * KSA * 64 + l64;
+                for (int k0 = 0; k0 < KSA; k0 += 8) {
+                    double av[8], bv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool in = k0 + u < KSA;
+                        av[u] = in ? ma[(size_t)(k0 + u) * 64] : 0.0;
+                        bv[u] = in ? Q[(4 * (k0 + u) + (l64 >> 4)) * P + (l64 & 15)] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u += 2) {
+                        if (k0 + u < KSA) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+                        if (k0 + u + 1 < KSA) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                    }
+                }
+            }
+            acc += acc2;
+            tile_store(Y, P, t * 16, 0, acc, nb);
+        }
+        __syncthreads();
+        PHASE(2);
+        // Z_g = M_blk^T Y_blk (sJ16 x P), column tile tj of M per work item
+        {
+            double* Zp = Zp_all + (size_t)wg * sJ16 * P;
+            const int nks = nt_rows * 4;
+            for (int tj = w4; tj < ntj; tj += 4) {
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+                const int jj = 16 * tj + (l64 & 15);
+                const double* mcol = Mb + (size_t)(jj >> 2) * 64 + ((jj & 3) << 4);
+                for (int k0 = 0; k0 < nks; k0 += 8) {
+                    double av[8], yv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool in = k0 + u < nks;
+                        const int ii = 4 * (k0 + u) + (l64 >> 4);
+                        av[u] = in ? mcol[(size_t)(ii >> 4) * KSA * 64 + (ii & 15)] : 0.0;
+                        yv[u] = in ? Y[ii * P + (l64 & 15)] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < nks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], yv[u], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Zp[(size_t)(16 * tj + (l64 >> 4) + 4 * v) * P + (l64 & 15)] = acc[v];
+            }
+        }
+        mm_small<P, true, false>(Y, P, Y, P, Gy, bs16, scr);
+        mm_small<P, true, false>(Y, P, Ab, P, H, bs16, scr);
+        {
+            double* Gp = a.Gp + (size_t)wg * 2 * P * P;
+            for (int e = tid; e < P * P; e += NT) {
+                Gp[e] = Gy[e];
+                Gp[P * P + e] = H[e];
+            }
+        }
+        PHASE(3);
+        ++nbar;
+        grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        PHASE(4);
+        // reduce-scatter: full Gy and H, this workgroup's slice of Z
+        reduce_parts<G>(a.Gp, (size_t)2 * P * P, 2 * P * P, Gy);
+        reduce_parts<G>(Zp_all + (size_t)z0 * P, (size_t)sJ16 * P, zn * P, Zs);
+        __syncthreads();
+        // residual of the slice: ||Z - Q Gy||^2 over rows z0 .. z1
+        double part = 0.0;
+        for (int e = tid; e < zn * P; e += NT) {
+            const int i = e / P, c = e - i * P;
+            double q = 0.0;
+#pragma unroll
+            for (int d = 0; d < P; ++d) q = __builtin_fma(Q[(z0 + i) * P + d], Gy[d * P + c], q);
+            const double dz = Zs[e] - q;
+            part = __builtin_fma(dz, dz, part);
+        }
+        for (int e = tid; e < zn * P; e += NT) a.Zr[(size_t)z0 * P + e] = Zs[e];
+        const double num_s = block_sum(part, red);
+        if (tid == 0) a.rp[wg] = num_s;
+        PHASE(5);
+        ++nbar;
+        grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        double gn = 0.0;
+        for (int e = tid; e < P * P; e += NT) gn = __builtin_fma(Gy[e], Gy[e], gn);
+        const double den = block_sum(gn, red);
+        double num = 0.0;
+        for (int g = 0; g < G; ++g) num += a.rp[g];
+        rho = den > 0.0 ? __builtin_sqrt(num / den) : 0.0;
+        ++it;
+        conv = !(rho > a.tol);
+        PHASE(6);
+        if (conv || it >= a.max_it) break;
+        // all-gather: Q <- orth(Z)
+        batched(sJ16 * P, [&](int e) { return e < sJ * P ? a.Zr[e] : 0.0; }, [&](int e, double v) { Q[e] = v; });
+        __syncthreads();
+        orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red,
+                          a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
+        PHASE(7);
+    }
+
+    // ---- epilogue ---------------------------------------------------------
+    const double ptol = 4.0 * (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
+    chol_inv<P>(Gy, Ls, Li, dead, ptol);
+    mm_rows<P, false, true>(Y, P, Li, P, Wb, P, bs16, P, nb);     // Wt = Y Ly^-T (this block)
+    for (int e = tid; e < P * P; e += NT) {
+        const int i = e / P, j = e - i * P;
+        double g = 0.0;
+        for (int k = 0; k < P; ++k) g = __builtin_fma(Li[i * P + k], H[k * P + j], g);
+        Gam[e] = g;
+        TA[e] = Li[j * P + i];
+    }
+    __syncthreads();
+    mm_small<P, false, false>(a.Bsc, sJ16, Q, P, Gam2, sJ16, scr);   // Gamma' = B_k[:, J] Q
+    PHASE(8);
+    mm_rows<P, false, false>(Wb, P, Gam, P, Y, P, bs16, P, nb);     // Delta_blk (into Y)
+    __syncthreads();
+    for (int e = tid; e < nb * R; e += NT) {
+        const int ar = e / R, c = e - ar * R;
+        const int64_t base = (int64_t)(a0 + ar) * a.qs;
+        fput(a.rowI, base + c, Ab[ar * P + c], fd);
+        fput(a.rowI, base + R + c, Wb[ar * P + c], fd);
+        fput(a.rowI, base + 2 * R + c, Ab[ar * P + c] - Y[ar * P + c], fd);
+        a.W[(int64_t)(a0 + ar) * R + c] = Wb[ar * P + c];
+    }
+    const int nbj = (sJ - wg + G - 1) / G;
+    for (int e = tid; e < nbj * R; e += NT) {
+        const int b = wg + G * (e / R), c = e % R;
+        double s = 0.0;
+        for (int i = 0; i < P; ++i) s = __builtin_fma(Gam2[c * P + i], Q[b * P + i], s);
+        const int64_t base = (int64_t)b * a.qs;
+        const double bcj = a.Bsc[(size_t)c * sJ16 + b];
+        fput(a.rowJ, base + c, bcj, fd);
+        fput(a.rowJ, base + R + c, Q[b * P + c], fd);
+        fput(a.rowJ, base + 2 * R + c, bcj - s, fd);
+        a.V[(int64_t)b * R + c] = Q[b * P + c];
+        if (a.prevV_out) a.prevV_out[(int64_t)b * R + c] = Q[b * P + c];
+    }
+    if (wg == 0) {
+        for (int e = tid; e < R * R; e += NT) {
+            const int c = e / R, d = e - c * R;
+            fput(a.GmI, e, Gam[c * P + d], fd);
+            fput(a.GmJ, e, Gam2[d * P + c], fd);
+            fput(a.scaleJ, e, TA[c * P + d], fd);
+            if (a.TAd) a.TAd[e] = TA[c * P + d];
+            a.sigma[e] = Ls[d * P + c];
+        }
+        if (tid == 0) {
+            int kept = 0;
+            for (int i = 0; i < r; ++i) kept += dead[i] == 0 ? 1 : 0;
+            a.info->iters = it;
+            a.info->kept = kept;
+            a.info->resid = rho;
+            a.info->gap = -1.0;
+            if (!conv) a.st->svd_capped = 1;
+            if (kept < r && Gy[0] > 0.0) a.st->rank_drop = 1;
+        }
+    }
+    PHASE(11);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void svdl_kernel(SvdArgs a) {
+    svdl_body<G>(a, blockIdx.x);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void svdl_batch_kernel(const SvdArgs* __restrict__ arr) {
+    const SvdArgs a = arr[blockIdx.y];
+    svdl_body<G>(a, blockIdx.x);
+}
+
 hipError_t launch_svd(const SvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s) {
     SvdArgs b = a;
     b.warm = (a.warm & 0xff) | ((dtype == 0 ? 0 : 1) << 8);
@@ -463,6 +761,41 @@ hipError_t launch_svd_batch(const SvdArgs* arr_dev, int nb, int G, int P, size_t
 #undef IRCUR_SVDB_CASE
     if (!fn || nb < 1) return hipErrorInvalidValue;
     static bool attr_set[4] = {false, false, false, false};
+    if (!attr_set[slot]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set[slot] = true;
+    }
+    void* args[] = {(void*)&arr_dev};
+    return hipLaunchKernel(fn, dim3(G, nb), dim3(NT), args, lds_bytes, s);
+}
+
+hipError_t launch_svdl(const SvdArgs& a, size_t lds_bytes, hipStream_t s) {
+    const void* fn = nullptr;
+    int slot = -1;
+    if (a.G == 8) { fn = (const void*)svdl_kernel<8>; slot = 0; }
+    if (a.G == 16) { fn = (const void*)svdl_kernel<16>; slot = 1; }
+    if (a.G == 32) { fn = (const void*)svdl_kernel<32>; slot = 2; }
+    if (!fn || a.p != 16) return hipErrorInvalidValue;
+    static bool attr_set[3] = {false, false, false};
+    if (!attr_set[slot]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set[slot] = true;
+    }
+    SvdArgs b = a;
+    void* args[] = {&b};
+    return hipLaunchKernel(fn, dim3(a.G), dim3(NT), args, lds_bytes, s);
+}
+
+hipError_t launch_svdl_batch(const SvdArgs* arr_dev, int nb, int G, size_t lds_bytes, hipStream_t s) {
+    const void* fn = nullptr;
+    int slot = -1;
+    if (G == 2) { fn = (const void*)svdl_batch_kernel<2>; slot = 0; }
+    if (G == 4) { fn = (const void*)svdl_batch_kernel<4>; slot = 1; }
+    if (G == 8) { fn = (const void*)svdl_batch_kernel<8>; slot = 2; }
+    if (!fn || nb < 1) return hipErrorInvalidValue;
+    static bool attr_set[3] = {false, false, false};
     if (!attr_set[slot]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
