@@ -498,8 +498,8 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->esz = p.dtype == IRCUR_F64 ? 8 : (p.dtype == IRCUR_F32 ? 4 : 2);
     c->fsz = p.dtype == IRCUR_F64 ? 8 : 4;
     c->D = D_dev;
-    c->nwg_row = (int)((p.n2 + 63) / 64);
-    c->nwg_col = (int)((p.n1 + 63) / 64);
+    c->nwg_row = (int)((p.n2 + pass_cols(p.dtype) - 1) / pass_cols(p.dtype));
+    c->nwg_col = (int)((p.n1 + pass_cols(p.dtype) - 1) / pass_cols(p.dtype));
 
 #define TRY(x)                      \
     do {                            \

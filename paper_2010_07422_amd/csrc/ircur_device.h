@@ -69,70 +69,106 @@ __device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
     return F(1) / (F(1) + exp_t(-(ax - zeta) / tauz));
 }
 
-// One workgroup: 64 consecutive outputs (one per lane) x all s gathered rows.
-// Wave w takes a contiguous quarter of the rows and keeps U row loads of D in
-// flight (the next group is issued before the current one is consumed); the
-// four partial sums are reduced in LDS at the end.  The per-row data
-// (gathered factor row, projection row, Delta row; QS elements per row, 16-byte
-// aligned) is wave-uniform: the workgroup stages it in LDS with batched
-// 16-byte loads (all rows at once unless they exceed the LDS budget) and reads
-// it back as broadcast loads.  The index arrays carry kIndexPad valid trailing
-// entries, so a group may read past the end of a wave's rows.
-template <typename T> struct RowsInFlight { static constexpr int value = 32; };
-template <> struct RowsInFlight<bf16_t> { static constexpr int value = 64; };
-template <> struct RowsInFlight<double> { static constexpr int value = 16; };
+// One workgroup: 64 V consecutive outputs (V per lane: 2 for BF16 so that a
+// wave reads 256-byte row segments, 1 otherwise) x all s gathered rows.  The
+// NW waves split the rows into contiguous chunks; each keeps U row loads in
+// flight.  The per-wave partial sums are combined by a fixed binary tree in
+// LDS (the result does not depend on scheduling).  The per-row data
+// (gathered factor row, projection row, Delta row; QS elements per row,
+// 16-byte aligned) is wave-uniform: the workgroup stages it in LDS with
+// batched 16-byte loads (all rows at once unless they exceed the stage budget)
+// and reads it back as broadcast loads.  The index arrays carry kIndexPad
+// valid trailing entries, so a group may read past the end of a wave's rows.
+template <typename T> struct RowsInFlight { static constexpr int value = 16; };
+template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
+template <> struct RowsInFlight<double> { static constexpr int value = 8; };
+template <typename T> struct ColsPerLane { static constexpr int value = 1; };
+template <> struct ColsPerLane<bf16_t> { static constexpr int value = 2; };
+// Waves per pass workgroup: 16 for BF16 (half as many workgroups, 128 columns
+// each), 8 otherwise.
+template <typename T, int R> struct PassWaves { static constexpr int value = 8; };
+template <int R> struct PassWaves<bf16_t, R> { static constexpr int value = R <= 12 ? 16 : 8; };
+
+// Static LDS of the pass (bytes): one stage of the reduction tree.
+template <typename T, typename F, int R> struct PassTree {
+    static constexpr int V = ColsPerLane<T>::value;
+    static constexpr int slots = PassWaves<T, R>::value / 2;
+    static constexpr int nred = slots * R * 64 * V;          // F values
+    static constexpr int nzd = slots * 64 * 2;               // doubles (zz, dd)
+    static constexpr size_t bytes = (size_t)nred * sizeof(F) + (size_t)nzd * sizeof(double);
+};
+
+// Element loads of one row for the V columns of a lane.
+template <typename T, typename F, int V>
+__device__ __forceinline__ void load_row(const T* __restrict__ row, int64_t col0, int nvalid, bool vec, F* out) {
+    if (V == 1) {
+        out[0] = ld<T, F>(row + (nvalid > 0 ? col0 : 0));
+    } else {
+        if (vec && nvalid == V) {
+            const uint32_t u = *(const uint32_t*)(row + col0);
+            out[0] = __uint_as_float(u << 16);
+            out[1] = __uint_as_float(u & 0xffff0000u);
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) out[v] = ld<T, F>(row + (v < nvalid ? col0 + v : 0));
+        }
+    }
+}
 
 template <typename T, typename F, int R, bool LIT, bool GATE = false>
 __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta, float zeta_f,
-                                          F (*red)[R][64], double (*redz)[64], double (*redd)[64],
-                                          F* qstage, int segmax, F tauz = F(0)) {
+                                          F* red, double* redzd, F* qstage, int segmax, F tauz = F(0)) {
+    constexpr int NW = PassWaves<T, R>::value;
+    constexpr int V = ColsPerLane<T>::value;
     constexpr int U = RowsInFlight<T>::value;
     static_assert(U <= kIndexPad, "the row read-ahead must stay inside the index padding");
+    static_assert(V == 1 || sizeof(T) == 2, "two columns per lane only for 16-bit storage");
     constexpr int QS = RowStride<F, R>::value;
     constexpr int UPR = QS * (int)sizeof(F) / 16;          // 16-byte units per row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t col = (int64_t)wg * 64 + lane;
-    const bool valid = col < S.n;
     const int64_t n = S.n;
+    const int64_t col0 = ((int64_t)wg * 64 + lane) * V;
+    int nvalid = (int)(n - col0);
+    if (nvalid < 0) nvalid = 0;
+    if (nvalid > V) nvalid = V;
     const T* __restrict__ X = (const T*)S.X;
     const F* __restrict__ P = (const F*)S.P;
     const u32x4* __restrict__ rd4 = (const u32x4*)S.rowdata;
     const int32_t* __restrict__ rows = S.rows;
     const int64_t ldX = S.ldX;
+    const bool vec = (ldX % 2) == 0;                         // aligned pairs in every row
 
-    F p[R];
+    F p[V][R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) p[c] = valid ? P[c * n + col] : F(0);
-    F acc[R];
+    for (int v = 0; v < V; ++v)
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = F(0);
+        for (int c = 0; c < R; ++c) p[v][c] = v < nvalid ? P[c * n + col0 + v] : F(0);
+    F acc[V][R];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[v][c] = F(0);
     F zz = F(0), dd = F(0);
-    const T* __restrict__ Xc = X + (valid ? col : 0);   // invalid lanes read column 0
-    const int chunk = (S.s + 3) >> 2;
+    const int chunk = (S.s + NW - 1) / NW;
     const int a_begin = wave * chunk;
     const int a_end = min(S.s, a_begin + chunk);
-    // rows per stage: whole chunk if it fits, else segmax (a multiple of U)
-    const int SEG = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    // rows per stage: the whole chunk if it fits, else segmax (a multiple of U)
+    const int SEG = chunk <= segmax ? chunk : segmax;
     F* __restrict__ qw = qstage + wave * (SEG * QS);
 
-    F dv[U];
-    if (a_end > a_begin) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) dv[u] = ld<T, F>(Xc + (int64_t)rows[a_begin + u] * ldX);
-    }
     for (int seg0 = 0; seg0 < chunk; seg0 += SEG) {       // uniform over the workgroup
         const int sb = a_begin + seg0;
         const int se = min(a_end, sb + SEG);
         __syncthreads();                                  // previous segment consumed
         {
-            const int units = 4 * SEG * UPR;
-            for (int base = threadIdx.x; base < units; base += 256 * 8) {
-                u32x4 v[8];
-                int dst[8];
+            const int units = NW * SEG * UPR;
+            for (int base = threadIdx.x; base < units; base += 64 * NW * 4) {
+                u32x4 v[4];
+                int dst[4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int un = base + u * 256;
+                for (int u = 0; u < 4; ++u) {
+                    const int un = base + u * 64 * NW;
                     int64_t src = 0;
                     bool ok = false;
                     if (un < units) {
@@ -147,81 +183,103 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
                     v[u] = rd4[ok ? src : 0];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < 4; ++u)
                     if (dst[u] >= 0) ((u32x4*)qstage)[dst[u]] = v[u];
             }
         }
         __syncthreads();
         for (int a0 = sb; a0 < se; a0 += U) {
-            F cur[U];
+            F dv[U][V];
 #pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = dv[u];
-            if (a0 + U < a_end) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) dv[u] = ld<T, F>(Xc + (int64_t)rows[a0 + U + u] * ldX);
-            }
+            for (int u = 0; u < U; ++u) load_row<T, F, V>(X + (int64_t)rows[a0 + u] * ldX, col0, nvalid, vec, dv[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int a = a0 + u;
                 if (a < se) {
-                    const F d = valid ? cur[u] : F(0);
                     const F* q = qw + (a - sb) * QS;
-                    F dot = F(0);
+                    F qa[3 * R];
 #pragma unroll
-                    for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c], dot);
-                    const F x = d - dot;
-                    F xr;
-                    if (GATE) xr = x - x * gate_value<F>(x, (F)zeta, tauz);
-                    else xr = above(x < F(0) ? -x : x, zeta, zeta_f) ? F(0) : x;
+                    for (int c = 0; c < (LIT ? 3 * R : 2 * R); ++c) qa[c] = q[c];
 #pragma unroll
-                    for (int c = 0; c < R; ++c) acc[c] = fmaT(q[R + c], xr, acc[c]);
-                    if (LIT) {
-                        F z = xr;
+                    for (int v = 0; v < V; ++v) {
+                        const F d = v < nvalid ? dv[u][v] : F(0);
+                        F dot = F(0);
 #pragma unroll
-                        for (int c = 0; c < R; ++c) z = fmaT(q[2 * R + c], p[c], z);
-                        zz = fmaT(z, z, zz);
-                    } else {
-                        zz = fmaT(xr, xr, zz);
+                        for (int c = 0; c < R; ++c) dot = fmaT(qa[c], p[v][c], dot);
+                        const F x = d - dot;
+                        F xr;
+                        if (GATE) xr = x - x * gate_value<F>(x, (F)zeta, tauz);
+                        else xr = above(x < F(0) ? -x : x, zeta, zeta_f) ? F(0) : x;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[v][c] = fmaT(qa[R + c], xr, acc[v][c]);
+                        if (LIT) {
+                            F z = xr;
+#pragma unroll
+                            for (int c = 0; c < R; ++c) z = fmaT(qa[2 * R + c], p[v][c], z);
+                            zz = fmaT(z, z, zz);
+                        } else {
+                            zz = fmaT(xr, xr, zz);
+                        }
+                        dd = fmaT(d, d, dd);
                     }
-                    dd = fmaT(d, d, dd);
                 }
             }
         }
     }
 
+    // fixed reduction tree over the waves: NW/2 -> ... -> 1
+    double zl = (double)zz, dl = (double)dd;
 #pragma unroll
-    for (int c = 0; c < R; ++c) red[wave][c][lane] = acc[c];
-    redz[wave][lane] = (double)zz;
-    redd[wave][lane] = (double)dd;
-    __syncthreads();
+    for (int half = NW / 2; half >= 1; half >>= 1) {
+        __syncthreads();
+        if (wave >= half && wave < 2 * half) {
+            const int slot = wave - half;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c) red[((slot * R + c) * V + v) * 64 + lane] = acc[v][c];
+            redzd[(slot * 2) * 64 + lane] = zl;
+            redzd[(slot * 2 + 1) * 64 + lane] = dl;
+        }
+        __syncthreads();
+        if (wave < half) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[v][c] += red[((wave * R + c) * V + v) * 64 + lane];
+            zl += redzd[(wave * 2) * 64 + lane];
+            dl += redzd[(wave * 2 + 1) * 64 + lane];
+        }
+    }
     if (wave == 0) {
         const F* __restrict__ Gm = (const F*)S.Gm;
         const F* __restrict__ Tm = (const F*)S.outmat;
         F* __restrict__ out = (F*)S.out;
         double corr = 0.0;
-        F val[R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const F g = ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
-            if (LIT) corr = __builtin_fma((double)g, (double)g, corr);
-            F base = F(0);
+        for (int v = 0; v < V; ++v) {
+            F val[R];
 #pragma unroll
-            for (int e = 0; e < R; ++e) base = fmaT(Gm[c * R + e], p[e], base);
-            val[c] = base + g;
-        }
+            for (int c = 0; c < R; ++c) {
+                const F g = acc[v][c];
+                if (LIT && v < nvalid) corr = __builtin_fma((double)g, (double)g, corr);
+                F base = F(0);
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-            F o = val[c];
-            if (Tm) {
-                o = F(0);
-#pragma unroll
-                for (int d = 0; d < R; ++d) o = fmaT(val[d], Tm[d * R + c], o);
+                for (int e = 0; e < R; ++e) base = fmaT(Gm[c * R + e], p[v][e], base);
+                val[c] = base + g;
             }
-            if (valid) out[c * n + col] = o;
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                F o = val[c];
+                if (Tm) {
+                    o = F(0);
+#pragma unroll
+                    for (int d = 0; d < R; ++d) o = fmaT(val[d], Tm[d * R + c], o);
+                }
+                if (v < nvalid) out[c * n + col0 + v] = o;
+            }
         }
-        double zl = ((redz[0][lane] + redz[1][lane]) + redz[2][lane]) + redz[3][lane];
-        double dl = ((redd[0][lane] + redd[1][lane]) + redd[2][lane]) + redd[3][lane];
-        if (!valid) { zl = 0.0; dl = 0.0; corr = 0.0; }
+        if (nvalid == 0) { zl = 0.0; dl = 0.0; corr = 0.0; }
         const double res = wave_sum(zl - corr);
         const double dsum = wave_sum(dl);
         if (lane == 0) {
@@ -230,6 +288,14 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
         }
     }
 }
+
+// LDS bytes left for the per-row data stage of a pass kernel with the given
+// static LDS (160 KiB per workgroup, 1 KiB margin, at most kPassStageBytes).
+inline int pass_stage_budget(size_t static_bytes) {
+    const long b = 160L * 1024 - (long)static_bytes - 1024;
+    return (int)(b < kPassStageBytes ? b : kPassStageBytes);
+}
+
 
 #define IRCUR_RANK_SWITCH(FN, T, F, R, ...)                     \
     switch (R) {                                                \

@@ -104,19 +104,17 @@ __global__ __launch_bounds__(256) void core_kernel(CoreArgs a) {
 // ----------------------------------------------------------------- pass ---
 
 template <typename T, typename F, int R, bool LIT>
-__global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
+__global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(PassArgs a) {
     if (a.st->stop) return;
-    __shared__ F red[4][R][64];
-    __shared__ double redz[4][64];
-    __shared__ double redd[4][64];
+    __shared__ F red[PassTree<T, F, R>::nred];
+    __shared__ double redzd[PassTree<T, F, R>::nzd];
     extern __shared__ __align__(16) unsigned char dyn[];
     F* qstage = (F*)dyn;
     const int wg = blockIdx.x;
     if (wg < a.side[0].nwg)
-        side_body<T, F, R, LIT>(a.side[0], wg, a.zeta, a.zeta_f, red, redz, redd, qstage, a.segmax);
+        side_body<T, F, R, LIT>(a.side[0], wg, a.zeta, a.zeta_f, red, redzd, qstage, a.segmax);
     else
-        side_body<T, F, R, LIT>(a.side[1], wg - a.side[0].nwg, a.zeta, a.zeta_f, red, redz, redd, qstage,
-                                a.segmax);
+        side_body<T, F, R, LIT>(a.side[1], wg - a.side[0].nwg, a.zeta, a.zeta_f, red, redzd, qstage, a.segmax);
 }
 
 // ------------------------------------------------------------- finalize ---
@@ -177,23 +175,24 @@ static hipError_t pass_r(const PassArgs& a0, hipStream_t s) {
     PassArgs a = a0;
     constexpr int U = RowsInFlight<T>::value;
     constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
-    int segmax = (kPassStageBytes / (4 * rowbytes)) / U * U;
+    const int budget = pass_stage_budget(PassTree<T, F, R>::bytes);
+    int segmax = (budget / (PassWaves<T, R>::value * rowbytes)) / U * U;
     if (segmax < U) segmax = U;
-    const int chunk = (std::max(a.side[0].s, a.side[1].s) + 3) / 4;
-    const int seg = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
+    const int chunk = (std::max(a.side[0].s, a.side[1].s) + PassWaves<T, R>::value - 1) / PassWaves<T, R>::value;
+    const int seg = chunk <= segmax ? chunk : segmax;
     a.segmax = segmax;
-    const size_t lds = (size_t)4 * seg * rowbytes;
+    const size_t lds = (size_t)PassWaves<T, R>::value * seg * rowbytes;
     static bool attr[2] = {false, false};
     const int li = a.err_mode == 0 ? 0 : 1;
     const void* fn = a.err_mode == 0 ? (const void*)pass_kernel<T, F, R, true> : (const void*)pass_kernel<T, F, R, false>;
     if (!attr[li]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kPassStageBytes);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, budget);
         if (e != hipSuccess) return e;
         attr[li] = true;
     }
     const unsigned grid = (unsigned)(a.side[0].nwg + a.side[1].nwg);
-    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 256, lds, s>>>(a);
-    else pass_kernel<T, F, R, false><<<grid, 256, lds, s>>>(a);
+    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 64 * PassWaves<T, R>::value, lds, s>>>(a);
+    else pass_kernel<T, F, R, false><<<grid, 64 * PassWaves<T, R>::value, lds, s>>>(a);
     return hipGetLastError();
 }
 

@@ -105,11 +105,11 @@ __global__ __launch_bounds__(256) void ucore_kernel(const CoreArgs* __restrict__
 }
 
 template <typename T, typename F, int R, bool GATE>
-__global__ __launch_bounds__(256) void upass_kernel(const PassArgs* __restrict__ arr, const int32_t* __restrict__ off,
-                                                    int nb, const double* __restrict__ zk, double tau_rel) {
-    __shared__ F red[4][R][64];
-    __shared__ double redz[4][64];
-    __shared__ double redd[4][64];
+__global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void upass_kernel(const PassArgs* __restrict__ arr,
+                                                               const int32_t* __restrict__ off, int nb,
+                                                               const double* __restrict__ zk, double tau_rel) {
+    __shared__ F red[PassTree<T, F, R>::nred];
+    __shared__ double redzd[PassTree<T, F, R>::nzd];
     extern __shared__ __align__(16) unsigned char dyn[];
     const int b = find_inst(off, nb, blockIdx.x);
     const PassArgs& a = arr[b];
@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void upass_kernel(const PassArgs* __restrict__
     const float zf = round_down_f(zeta);
     const F tz = (F)(tau_rel * zeta);
     if (local < a.side[0].nwg)
-        side_body<T, F, R, false, GATE>(a.side[0], local, zeta, zf, red, redz, redd, (F*)dyn, a.segmax, tz);
+        side_body<T, F, R, false, GATE>(a.side[0], local, zeta, zf, red, redzd, (F*)dyn, a.segmax, tz);
     else
-        side_body<T, F, R, false, GATE>(a.side[1], local - a.side[0].nwg, zeta, zf, red, redz, redd, (F*)dyn,
+        side_body<T, F, R, false, GATE>(a.side[1], local - a.side[0].nwg, zeta, zf, red, redzd, (F*)dyn,
                                         a.segmax, tz);
 }
 
@@ -777,7 +777,7 @@ template <typename T, typename F, int R>
 int upass_segmax_r() {
     constexpr int U = RowsInFlight<T>::value;
     constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
-    int segmax = (kPassStageBytes / (4 * rowbytes)) / U * U;
+    const int segmax = (pass_stage_budget(PassTree<T, F, R>::bytes) / (PassWaves<T, R>::value * rowbytes)) / U * U;
     return segmax < U ? U : segmax;
 }
 
@@ -786,20 +786,21 @@ hipError_t upass_r(const PassArgs* arr, const int32_t* off, int nb, int total, i
                    double tau, hipStream_t s) {
     constexpr int U = RowsInFlight<T>::value;
     constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
+    const int budget = pass_stage_budget(PassTree<T, F, R>::bytes);
     const int segmax = upass_segmax_r<T, F, R>();
-    const int chunk = (max_s + 3) / 4;
-    const int seg = chunk <= segmax ? ((chunk + U - 1) / U) * U : segmax;
-    const size_t lds = (size_t)4 * seg * rowbytes;
+    const int chunk = (max_s + PassWaves<T, R>::value - 1) / PassWaves<T, R>::value;
+    const int seg = chunk <= segmax ? chunk : segmax;
+    const size_t lds = (size_t)PassWaves<T, R>::value * seg * rowbytes;
     static bool attr[2] = {false, false};
     const int gi = tau > 0.0 ? 1 : 0;
     const void* fn = tau > 0.0 ? (const void*)upass_kernel<T, F, R, true> : (const void*)upass_kernel<T, F, R, false>;
     if (!attr[gi]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kPassStageBytes);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, budget);
         if (e != hipSuccess) return e;
         attr[gi] = true;
     }
-    if (tau > 0.0) upass_kernel<T, F, R, true><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
-    else upass_kernel<T, F, R, false><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
+    if (tau > 0.0) upass_kernel<T, F, R, true><<<total, 64 * PassWaves<T, R>::value, lds, s>>>(arr, off, nb, zk, tau);
+    else upass_kernel<T, F, R, false><<<total, 64 * PassWaves<T, R>::value, lds, s>>>(arr, off, nb, zk, tau);
     return hipGetLastError();
 }
 

@@ -43,6 +43,10 @@ struct UHost {
     double* MB = nullptr;
     double* Zp = nullptr;
     double* Gp = nullptr;
+    double* Abc = nullptr;      // compact A_k[I, :] (sI16 x 16)
+    double* Bsc = nullptr;      // compact B_k[:, J] (16 x sJ16)
+    double* Zr = nullptr;       // reduced Z of the SVD (sJ16 x 16)
+    double* rp = nullptr;       // SVD residual parts (G)
     double* W = nullptr;        // K x sI x R
     double* V = nullptr;        // K x sJ x R
     double* Kc = nullptr;       // K x R x R
@@ -183,12 +187,14 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
         u->max_sI16 = std::max(u->max_sI16, (in.sI + 15) / 16 * 16);
         u->max_sJ16 = std::max(u->max_sJ16, (in.sJ + 15) / 16 * 16);
     }
-    // SVD workgroups per core: the fewest of 1, 2, 4, 8 whose LDS layout fits
+    // SVD workgroups per core: the fewest of 2, 4, 8 whose LDS layout (row
+    // block of M resident in LDS) fits; all workgroups of the batch are
+    // co-resident (one per CU)
     {
         bool ok = false;
-        for (int g : {1, 2, 4, 8}) {
+        for (int g : {2, 4, 8}) {
             const int bs16 = 16 * ((u->max_sI16 / 16 + g - 1) / g);
-            const size_t lds = svd_lds_bytes(u->max_sJ16, bs16, 16);
+            const size_t lds = svdl_lds_bytes(u->max_sJ16, bs16, g);
             if (lds <= 160 * 1024) {
                 u->G = g;
                 u->max_bs16 = bs16;
@@ -197,7 +203,6 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
                 break;
             }
         }
-        // all workgroups of one core are co-resident: keep the batch within one per CU
         if (!ok || (size_t)u->G * nb > 256) { delete u; return IRCUR_ERR_UNSUPPORTED; }
     }
     if (ubsmall_lds_bytes(std::max(u->max_sI16, u->max_sJ16)) > 160 * 1024) { delete u; return IRCUR_ERR_UNSUPPORTED; }
@@ -223,7 +228,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
         const int64_t n1 = in.n1, n2 = in.n2;
         const int sI = in.sI, sJ = in.sJ;
         const int sI16 = (sI + 15) / 16 * 16, sJ16 = (sJ + 15) / 16 * 16;
-        h.nwg_row = (int)((n2 + 63) / 64);
+        h.nwg_row = (int)((n2 + 63) / 64);      // F64 / F32 storage: 64 columns per pass workgroup
         h.nwg_col = (int)((n1 + 63) / 64);
         h.nwgA = (int)std::min<int64_t>(64, (n1 + 127) / 128);
         h.nwgB = (int)std::min<int64_t>(64, (n2 + 127) / 128);
@@ -239,8 +244,12 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             h.M = cv.take<double>((size_t)K * sI * sJ);
             h.MA = cv.take<double>((size_t)sI16 * sJ16);
             h.MB = cv.take<double>((size_t)sI16 * sJ16);
-            h.Zp = cv.take<double>((size_t)G * sJ * P);
+            h.Zp = cv.take<double>((size_t)G * sJ16 * P);
             h.Gp = cv.take<double>((size_t)G * 2 * P * P);
+            h.Abc = cv.take<double>((size_t)sI16 * 16);
+            h.Bsc = cv.take<double>((size_t)16 * sJ16);
+            h.Zr = cv.take<double>((size_t)sJ16 * 16);
+            h.rp = cv.take<double>((size_t)G);
             h.W = cv.take<double>((size_t)K * sI * R);
             h.V = cv.take<double>((size_t)K * sJ * R);
             h.Kc = cv.take<double>((size_t)K * R * R);
@@ -364,7 +373,8 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             CoreArgs& ca = core[e];
             ca.D = in.D; ca.ldD = in.ldD; ca.I = Ik; ca.J = Jk; ca.sI = sI; ca.sJ = sJ;
             ca.n1 = in.n1; ca.n2 = in.n2; ca.At = At_k; ca.B = B_k;
-            ca.M = M_k; ca.MA = h.MA; ca.MB = h.MB; ca.st = st;
+            ca.M = M_k; ca.MA = h.MA; ca.MB = nullptr; ca.st = st;
+            ca.Abc = h.Abc; ca.Bsc = h.Bsc;
 
             SvdArgs& sa = svd[e];
             sa.MA = h.MA; sa.MB = h.MB; sa.sI = sI; sa.sJ = sJ; sa.r = u->r; sa.R = R; sa.p = 16;
@@ -382,6 +392,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             sa.GmI = h.GmI; sa.GmJ = h.GmJ; sa.scaleJ = h.scaleJ;
             sa.TAd = h.TAd + (size_t)k * R * R;
             sa.info = h.info + k; sa.st = st;
+            sa.Abc = h.Abc; sa.Bsc = h.Bsc; sa.Zr = h.Zr; sa.rp = h.rp;
 
             PassArgs& pa = pas[e];
             SideArgs& r0 = pa.side[0];
@@ -445,7 +456,7 @@ int ircur_unrolled_forward(ircur_unrolled* u, const double* zeta_dev, double* lo
         const size_t e = (size_t)k * nb;
         UCHK(u, launch_ucore(u->d_core + e, u->off_core, nb, u->tot_core, u->zeta + k, u->tau_rel, u->dtype, R,
                              u->stream));
-        UCHK(u, launch_svd_batch(u->d_svd + e, nb, u->G, 16, u->svd_lds, u->stream));
+        UCHK(u, launch_svdl_batch(u->d_svd + e, nb, u->G, u->svd_lds, u->stream));
         UCHK(u, launch_upass(u->d_pass + e, u->off_pass, nb, u->tot_pass, u->max_s, u->zeta + k, u->tau_rel,
                              u->dtype, R, u->stream));
     }
