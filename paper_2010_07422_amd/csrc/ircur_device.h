@@ -79,15 +79,16 @@ __device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
 // batched 16-byte loads (all rows at once unless they exceed the stage budget)
 // and reads it back as broadcast loads.  The index arrays carry kIndexPad
 // valid trailing entries, so a group may read past the end of a wave's rows.
-template <typename T> struct RowsInFlight { static constexpr int value = 16; };
+// Rows in flight per wave (the next group is loaded while the current one is
+// processed), columns per lane and waves per workgroup, by storage type.
+// (Measured on MI355X at n = 10^4: FP64 is fastest with 8 waves, BF16 and
+// FP32 with 4 waves and one column per lane.)
+template <typename T> struct RowsInFlight { static constexpr int value = 8; };
 template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
 template <> struct RowsInFlight<double> { static constexpr int value = 8; };
 template <typename T> struct ColsPerLane { static constexpr int value = 1; };
-template <> struct ColsPerLane<bf16_t> { static constexpr int value = 2; };
-// Waves per pass workgroup: 16 for BF16 (half as many workgroups, 128 columns
-// each), 8 otherwise.
-template <typename T, int R> struct PassWaves { static constexpr int value = 8; };
-template <int R> struct PassWaves<bf16_t, R> { static constexpr int value = R <= 12 ? 16 : 8; };
+template <typename T, int R> struct PassWaves { static constexpr int value = 4; };
+template <int R> struct PassWaves<double, R> { static constexpr int value = 8; };
 
 // Static LDS of the pass (bytes): one stage of the reduction tree.
 template <typename T, typename F, int R> struct PassTree {
@@ -157,6 +158,12 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     const int SEG = chunk <= segmax ? chunk : segmax;
     F* __restrict__ qw = qstage + wave * (SEG * QS);
 
+    F nx[U][V];                                           // next group of rows (loaded ahead)
+    if (a_end > a_begin) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            load_row<T, F, V>(X + (int64_t)rows[a_begin + u] * ldX, col0, nvalid, vec, nx[u]);
+    }
     for (int seg0 = 0; seg0 < chunk; seg0 += SEG) {       // uniform over the workgroup
         const int sb = a_begin + seg0;
         const int se = min(a_end, sb + SEG);
@@ -191,7 +198,14 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
         for (int a0 = sb; a0 < se; a0 += U) {
             F dv[U][V];
 #pragma unroll
-            for (int u = 0; u < U; ++u) load_row<T, F, V>(X + (int64_t)rows[a0 + u] * ldX, col0, nvalid, vec, dv[u]);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) dv[u][v] = nx[u][v];
+            if (a0 + U < a_end) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    load_row<T, F, V>(X + (int64_t)rows[a0 + U + u] * ldX, col0, nvalid, vec, nx[u]);
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int a = a0 + u;

@@ -23,9 +23,8 @@ template <typename F, int R> struct RowStride {
 inline int row_stride(int R, int fsz) { return ((3 * R * fsz + 15) / 16) * (16 / fsz); }
 // LDS budget of the pass kernel's per-row data stage.
 constexpr int kPassStageBytes = 96 * 1024;
-// Output columns of one pass workgroup: 64 lanes x 2 columns for BF16 storage
-// (256-byte row segments), 64 x 1 otherwise.
-constexpr int pass_cols(int dtype) { return dtype == 2 ? 128 : 64; }
+// Output columns of one pass workgroup (64 lanes, one column each).
+constexpr int pass_cols(int) { return 64; }
 
 inline int pad_rank(int r) {
     for (int v : kRanks) if (v >= r) return v;
