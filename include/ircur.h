@@ -81,7 +81,8 @@ typedef struct {
     int32_t max_iter;    /* iteration cap, >= 1                                     */
     uint64_t seed;       /* index-sampler seed (SplitMix64 stream, see below)       */
     double  svd_tol;     /* relative residual tolerance of the top-r SVD; 0: default
-                            (1e-12 for F64, 1e-9 otherwise)                        */
+                            (1e-13 for F64, 1e-9 for F32, 1e-7 for BF16: four or
+                            more orders below the rounding of the stored D)        */
     int32_t svd_max_it;  /* subspace-iteration cap of the top-r SVD; 0: default 64   */
     int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default       */
 } ircur_params;
@@ -216,6 +217,21 @@ int ircur_set_state(ircur_ctx* ctx, const void* buf, size_t bytes);
  */
 int ircur_set_timing(ircur_ctx* ctx, int32_t enable);
 int ircur_get_timing(ircur_ctx* ctx, double* ms4, int64_t* count);
+
+/*
+ * Duration of the fused row/column pass (Algorithm 1, Phase II: the products
+ * of eq. (3) on the sampled rows and columns with the threshold of eq. (4)
+ * applied in the same pass) measured with HIP events on the context's stream:
+ * the pass of the last finished iteration k-1 is launched `reps` times back to
+ * back between two events and the mean per launch, in microseconds, is
+ * written to *us_out.  Each launch reads A_{k-1}, B_{k-1}, the iteration's
+ * index sets and the svd's per-row data, all still in place, and rewrites
+ * A_k, B_k and the stopping-test partial sums with the same values, so the
+ * state is unchanged.  ERR_STATE if no iteration has finished since
+ * init/reset/set_factors/set_state or the run has stopped; ERR_ARG for
+ * reps < 1.  Synchronises.
+ */
+int ircur_time_pass(ircur_ctx* ctx, int32_t reps, double* us_out);
 
 /* Diagnostics of the last iteration: svd iterations, svd residual, the
  * estimated gap sigma_{r+1}/sigma_r, kept rank.  Synchronises. */

@@ -130,6 +130,10 @@ struct ircur_ctx {
     double* part_row = nullptr;
     double* part_col = nullptr;
     int nwg_row = 0, nwg_col = 0;
+    int ns_row = 1, ns_col = 1;        // pass row blocks per column tile
+    void* pacc = nullptr;              // pass partial sums of row-split tiles
+    double* pzd = nullptr;
+    uint32_t* pcnt = nullptr;          // per-tile tickets (zero between launches)
     DevState* st = nullptr;
     DevState* st_host = nullptr;   // pinned
     SvdInfo* info = nullptr;       // max_iter records
@@ -148,6 +152,9 @@ struct ircur_ctx {
     bool timing = false;
     hipEvent_t ev[kRing][5];
     bool ev_made = false;
+    int32_t last_k = -1;                 // last enqueued iteration and its device index sets
+    const int32_t* lastIdev = nullptr;
+    const int32_t* lastJdev = nullptr;
     double tsum[4] = {0, 0, 0, 0};
     int64_t tcount = 0;
     std::string err;
@@ -222,7 +229,7 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
-                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->st,
+                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
                     c->info, c->hist};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -255,6 +262,7 @@ int reset_state(ircur_ctx* c) {
     c->acc_next = 0;
     c->stopped = false;
     c->have_prevV = false;
+    c->last_k = -1;
     c->lastJ.clear();
     c->tsum[0] = c->tsum[1] = c->tsum[2] = c->tsum[3] = 0.0;
     c->tcount = 0;
@@ -291,6 +299,29 @@ int status_after(ircur_ctx* c) {
     return IRCUR_OK;
 }
 
+// Arguments of the fused row/column pass of iteration k.
+PassArgs pass_args(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd) {
+    const ircur_params& p = c->p;
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double zeta = zeta_at(p, k);
+    PassArgs pa{};
+    SideArgs& r0 = pa.side[0];
+    r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
+    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outmat = nullptr; r0.out = c->B[nxt];
+    r0.part = c->part_row; r0.nwg = c->nwg_row;
+    const size_t fblk = pass_split_bytes(p.dtype, c->R) - 128 * sizeof(double);   // F sums per block
+    r0.nsplit = c->ns_row; r0.pacc = c->pacc; r0.pzd = c->pzd; r0.cnt = c->pcnt;
+    SideArgs& r1 = pa.side[1];
+    r1.X = c->Dt; r1.ldX = c->ldDt; r1.rows = Jd; r1.s = p.sJ; r1.n = p.n1; r1.P = c->At[cur];
+    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outmat = c->scaleJ; r1.out = c->At[nxt];
+    r1.part = c->part_col; r1.nwg = c->nwg_col;
+    const size_t nb0 = (size_t)c->nwg_row * c->ns_row;
+    r1.nsplit = c->ns_col; r1.pacc = (char*)c->pacc + nb0 * fblk; r1.pzd = c->pzd + nb0 * 128;
+    r1.cnt = c->pcnt + c->nwg_row;
+    pa.zeta = zeta; pa.zeta_f = round_down_float(zeta); pa.err_mode = p.err_mode; pa.st = c->st;
+    return pa;
+}
+
 // Enqueue iteration k (0-based) with the index sets already on the device.
 int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, const int32_t* Jhost) {
     const int slot = k % kRing;
@@ -322,7 +353,8 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.MA = c->MA; sa.MB = c->MB; sa.sI = p.sI; sa.sJ = p.sJ; sa.r = p.r; sa.R = c->R; sa.p = c->psvd;
     sa.G = c->G; sa.bs = c->bs;
     sa.max_it = p.svd_max_it > 0 ? p.svd_max_it : 64;
-    sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : 1e-9);
+    // default: well below the rounding of the stored D (bf16 keeps 8 bits)
+    sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : (p.dtype == IRCUR_F32 ? 1e-9 : 1e-7));
     bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
                  std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
     sa.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
@@ -347,16 +379,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     c->lastJ.assign(Jhost, Jhost + p.sJ);
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
 
-    PassArgs pa{};
-    SideArgs& r0 = pa.side[0];
-    r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
-    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outmat = nullptr; r0.out = c->B[nxt];
-    r0.part = c->part_row; r0.nwg = c->nwg_row;
-    SideArgs& r1 = pa.side[1];
-    r1.X = c->Dt; r1.ldX = c->ldDt; r1.rows = Jd; r1.s = p.sJ; r1.n = p.n1; r1.P = c->At[cur];
-    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outmat = c->scaleJ; r1.out = c->At[nxt];
-    r1.part = c->part_col; r1.nwg = c->nwg_col;
-    pa.zeta = zeta; pa.zeta_f = zf; pa.err_mode = p.err_mode; pa.st = c->st;
+    const PassArgs pa = pass_args(c, k, Id, Jd);
     HIPCHK(c, launch_pass(pa, p.dtype, c->R, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][3], s));
 
@@ -365,6 +388,9 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     fa.k = k; fa.max_iter = p.max_iter; fa.eps = p.eps; fa.hist = c->hist; fa.st = c->st;
     HIPCHK(c, launch_finalize(fa, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][4], s));
+    c->last_k = k;
+    c->lastIdev = Id;
+    c->lastJdev = Jd;
     return IRCUR_OK;
 }
 
@@ -569,6 +595,15 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     TRY(dalloc(c, &c->nnz, 1));
     TRY(dalloc(c, &c->part_row, (size_t)2 * c->nwg_row));
     TRY(dalloc(c, &c->part_col, (size_t)2 * c->nwg_col));
+    c->ns_row = pass_nsplit(p.dtype, c->R, p.sI, c->nwg_row);
+    c->ns_col = pass_nsplit(p.dtype, c->R, p.sJ, c->nwg_col);
+    {
+        const size_t nblk = (size_t)c->nwg_row * c->ns_row + (size_t)c->nwg_col * c->ns_col;
+        TRY(dalloc_bytes(c, &c->pacc, nblk * (pass_split_bytes(p.dtype, c->R) - 128 * sizeof(double))));
+        TRY(dalloc(c, &c->pzd, nblk * 128));
+        TRY(dalloc(c, &c->pcnt, (size_t)c->nwg_row + c->nwg_col));
+        HIPCHK(c, hipMemset(c->pcnt, 0, sizeof(uint32_t) * ((size_t)c->nwg_row + c->nwg_col)));
+    }
     TRY(dalloc(c, &c->st, 1));
     TRY(dalloc(c, &c->info, (size_t)p.max_iter));
     TRY(dalloc(c, &c->hist, (size_t)p.max_iter));
@@ -692,6 +727,7 @@ int ircur_set_factors(ircur_ctx* c, const void* At_dev, const void* B_dev, int32
     c->acc_next = k;
     c->stopped = false;
     c->have_prevV = false;
+    c->last_k = -1;
     return IRCUR_OK;
 }
 
@@ -828,7 +864,10 @@ int ircur_set_timing(ircur_ctx* c, int32_t enable) {
     c->acc_next = c->k;
     if (enable && !c->ev_made) {
         for (int i = 0; i < kRing; ++i)
-            for (int j = 0; j < 5; ++j) HIPCHK(c, hipEventCreate(&c->ev[i][j]));
+            // timing-only events: no system-scope fence (no cache write-back
+            // between the kernels that they bracket)
+            for (int j = 0; j < 5; ++j)
+                HIPCHK(c, hipEventCreateWithFlags(&c->ev[i][j], hipEventDisableSystemFence));
         c->ev_made = true;
     }
     c->timing = enable != 0;
@@ -841,6 +880,31 @@ int ircur_get_timing(ircur_ctx* c, double* ms4, int64_t* count) {
     if (!c || !ms4) return IRCUR_ERR_ARG;
     for (int q = 0; q < 4; ++q) ms4[q] = c->tsum[q];
     if (count) *count = c->tcount;
+    return IRCUR_OK;
+}
+
+int ircur_time_pass(ircur_ctx* c, int32_t reps, double* us_out) {
+    if (!c || reps < 1 || !us_out) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (c->k < 1 || c->stopped || c->last_k != c->k - 1)
+        return fail(c, IRCUR_ERR_STATE, "time_pass needs a finished iteration of a run that has not stopped");
+    // the pass of iteration k-1 reads A_{k-1}, B_{k-1} and the svd's per-row
+    // data, all still in place, and rewrites A_k, B_k with the same values
+    const PassArgs pa = pass_args(c, c->k - 1, c->lastIdev, c->lastJdev);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps && he == hipSuccess; ++i) he = launch_pass(pa, c->p.dtype, c->R, c->stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(c, IRCUR_ERR_DEVICE, hipGetErrorString(he));
+    *us_out = 1e3 * (double)ms / reps;
     return IRCUR_OK;
 }
 
@@ -895,6 +959,7 @@ int ircur_set_state(ircur_ctx* c, const void* buf, size_t bytes) {
     c->acc_next = k;
     c->stopped = hdr[2] != 0;
     c->have_prevV = false;
+    c->last_k = -1;
     return IRCUR_OK;
 }
 

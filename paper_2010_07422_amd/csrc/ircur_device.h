@@ -117,15 +117,14 @@ __device__ __forceinline__ void load_row(const T* __restrict__ row, int64_t col0
 }
 
 template <typename T, typename F, int R, bool LIT, bool GATE = false>
-__device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta, float zeta_f,
-                                          F* red, double* redzd, F* qstage, int segmax, F tauz = F(0)) {
+__device__ __forceinline__ void side_body(const SideArgs& S, int wg, int blk, double zeta, float zeta_f,
+                                          F* red, double* redzd, F tauz = F(0)) {
     constexpr int NW = PassWaves<T, R>::value;
     constexpr int V = ColsPerLane<T>::value;
     constexpr int U = RowsInFlight<T>::value;
     static_assert(U <= kIndexPad, "the row read-ahead must stay inside the index padding");
     static_assert(V == 1 || sizeof(T) == 2, "two columns per lane only for 16-bit storage");
     constexpr int QS = RowStride<F, R>::value;
-    constexpr int UPR = QS * (int)sizeof(F) / 16;          // 16-byte units per row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = S.n;
@@ -135,7 +134,6 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     if (nvalid > V) nvalid = V;
     const T* __restrict__ X = (const T*)S.X;
     const F* __restrict__ P = (const F*)S.P;
-    const u32x4* __restrict__ rd4 = (const u32x4*)S.rowdata;
     const int32_t* __restrict__ rows = S.rows;
     const int64_t ldX = S.ldX;
     const bool vec = (ldX % 2) == 0;                         // aligned pairs in every row
@@ -151,66 +149,43 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[v][c] = F(0);
     F zz = F(0), dd = F(0);
-    const int chunk = (S.s + NW - 1) / NW;
-    const int a_begin = wave * chunk;
-    const int a_end = min(S.s, a_begin + chunk);
-    // rows per stage: the whole chunk if it fits, else segmax (a multiple of U)
-    const int SEG = chunk <= segmax ? chunk : segmax;
-    F* __restrict__ qw = qstage + wave * (SEG * QS);
-
+    // this workgroup's rows [rb, re): row block blk of the tile, split over the waves
+    const int ns = S.nsplit > 1 ? S.nsplit : 1;
+    const int bsz = (S.s + ns - 1) / ns;
+    const int rb = min(S.s, blk * bsz);
+    const int re = min(S.s, rb + bsz);
+    const int chunk = (re - rb + NW - 1) / NW;
+    const int a_begin = rb + wave * chunk;
+    const int a_end = min(re, a_begin + chunk);
+    // the per-row data (gathered factor row, projection row, Delta row) is the
+    // same for every lane: it is read through the scalar cache into SGPRs,
+    // which the FMAs take as their uniform operand
+    typedef const __attribute__((address_space(4))) F* CF;
+    typedef const __attribute__((address_space(4))) int32_t* CI;
+    const CF rdc = (CF)S.rowdata;
+    const CI rowc = (CI)S.rows;
     F nx[U][V];                                           // next group of rows (loaded ahead)
     if (a_end > a_begin) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            load_row<T, F, V>(X + (int64_t)rows[a_begin + u] * ldX, col0, nvalid, vec, nx[u]);
+            load_row<T, F, V>(X + (int64_t)rowc[a_begin + u] * ldX, col0, nvalid, vec, nx[u]);
     }
-    for (int seg0 = 0; seg0 < chunk; seg0 += SEG) {       // uniform over the workgroup
-        const int sb = a_begin + seg0;
-        const int se = min(a_end, sb + SEG);
-        __syncthreads();                                  // previous segment consumed
-        {
-            const int units = NW * SEG * UPR;
-            for (int base = threadIdx.x; base < units; base += 64 * NW * 4) {
-                u32x4 v[4];
-                int dst[4];
+    for (int a0 = a_begin; a0 < a_end; a0 += U) {
+        F dv[U][V];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int un = base + u * 64 * NW;
-                    int64_t src = 0;
-                    bool ok = false;
-                    if (un < units) {
-                        const int w = un / (SEG * UPR);
-                        const int rem = un - w * (SEG * UPR);
-                        const int rr = rem / UPR, kk = rem - rr * UPR;
-                        const int row = w * chunk + seg0 + rr;
-                        ok = seg0 + rr < chunk && row < S.s;
-                        src = (int64_t)row * UPR + kk;
-                    }
-                    dst[u] = ok ? un : -1;
-                    v[u] = rd4[ok ? src : 0];
-                }
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (dst[u] >= 0) ((u32x4*)qstage)[dst[u]] = v[u];
-            }
-        }
-        __syncthreads();
-        for (int a0 = sb; a0 < se; a0 += U) {
-            F dv[U][V];
+            for (int v = 0; v < V; ++v) dv[u][v] = nx[u][v];
+        if (a0 + U < a_end) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
+                load_row<T, F, V>(X + (int64_t)rowc[a0 + U + u] * ldX, col0, nvalid, vec, nx[u]);
+        }
 #pragma unroll
-                for (int v = 0; v < V; ++v) dv[u][v] = nx[u][v];
-            if (a0 + U < a_end) {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    load_row<T, F, V>(X + (int64_t)rows[a0 + U + u] * ldX, col0, nvalid, vec, nx[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int a = a0 + u;
-                if (a < se) {
-                    const F* q = qw + (a - sb) * QS;
+        for (int u = 0; u < U; ++u) {
+            const int a = a0 + u;
+            if (a < a_end) {
+                const CF q = rdc + (size_t)a * QS;
                     F qa[3 * R];
 #pragma unroll
                     for (int c = 0; c < (LIT ? 3 * R : 2 * R); ++c) qa[c] = q[c];
@@ -236,7 +211,6 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
                         }
                         dd = fmaT(d, d, dd);
                     }
-                }
             }
         }
     }
@@ -263,6 +237,52 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
                 for (int c = 0; c < R; ++c) acc[v][c] += red[((wave * R + c) * V + v) * 64 + lane];
             zl += redzd[(wave * 2) * 64 + lane];
             dl += redzd[(wave * 2 + 1) * 64 + lane];
+        }
+    }
+    if (ns > 1) {
+        // row-split tile: publish this block's sums (device-scope stores, complete
+        // before the ticket is taken); the last block of the tile adds all blocks
+        // in block order, so the result does not depend on the arrival order
+        __shared__ int last_blk;
+        if (wave == 0) {
+            F* pa = (F*)S.pacc + (size_t)(wg * ns + blk) * (R * V * 64);
+            double* pz = S.pzd + (size_t)(wg * ns + blk) * 128;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c)
+                    __hip_atomic_store(pa + (c * V + v) * 64 + lane, acc[v][c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pz + lane, zl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pz + 64 + lane, dl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            if (lane == 0) {
+                const uint32_t t = __hip_atomic_fetch_add(S.cnt + wg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last_blk = t == (uint32_t)(ns - 1) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (!last_blk) return;
+        if (wave == 0) {
+            if (lane == 0) __hip_atomic_store(S.cnt + wg, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[v][c] = F(0);
+            zl = 0.0;
+            dl = 0.0;
+            for (int b = 0; b < ns; ++b) {
+                const F* pa = (const F*)S.pacc + (size_t)(wg * ns + b) * (R * V * 64);
+                const double* pz = S.pzd + (size_t)(wg * ns + b) * 128;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int c = 0; c < R; ++c)
+                        acc[v][c] += __hip_atomic_load(pa + (c * V + v) * 64 + lane, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                zl += __hip_atomic_load(pz + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                dl += __hip_atomic_load(pz + 64 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
     if (wave == 0) {
@@ -303,12 +323,6 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, double zeta
     }
 }
 
-// LDS bytes left for the per-row data stage of a pass kernel with the given
-// static LDS (160 KiB per workgroup, 1 KiB margin, at most kPassStageBytes).
-inline int pass_stage_budget(size_t static_bytes) {
-    const long b = 160L * 1024 - (long)static_bytes - 1024;
-    return (int)(b < kPassStageBytes ? b : kPassStageBytes);
-}
 
 
 #define IRCUR_RANK_SWITCH(FN, T, F, R, ...)                     \

@@ -21,8 +21,11 @@ template <typename F, int R> struct RowStride {
     static constexpr int value = ((3 * R * (int)sizeof(F) + 15) / 16) * (16 / (int)sizeof(F));
 };
 inline int row_stride(int R, int fsz) { return ((3 * R * fsz + 15) / 16) * (16 / fsz); }
-// LDS budget of the pass kernel's per-row data stage.
-constexpr int kPassStageBytes = 96 * 1024;
+// Row split of the pass: rows per row block (about 128, so that each wave
+// has a few groups of rows in flight) and the largest number of blocks per
+// column tile.
+constexpr int kPassSplitRows = 128;
+constexpr int kPassMaxSplit = 64;
 // Output columns of one pass workgroup (64 lanes, one column each).
 constexpr int pass_cols(int) { return 64; }
 
@@ -68,8 +71,16 @@ struct SideArgs {
     const void* Gm;        // R x R: Gamma (side 0) or Gamma'^T (side 1)
     const void* outmat;    // R x R map applied to the output row (nullptr: identity)
     void* out;             // new factor, R x n, row stride n
-    double* part;          // 2 doubles per workgroup: (residual, ||D_side||^2)
-    int32_t nwg;
+    double* part;          // 2 doubles per column tile: (residual, ||D_side||^2)
+    int32_t nwg;           // column tiles (64 V columns each)
+    // row split: nsplit workgroups per column tile, each over a block of
+    // ceil(s / nsplit) rows; their partial sums meet in pacc/pzd and the last
+    // workgroup of the tile to finish (ticket in cnt) adds them in block order
+    // and writes the tile's output.  nsplit <= 1: one workgroup per tile.
+    int32_t nsplit;
+    void* pacc;            // nwg x nsplit x R x V x 64 (F)
+    double* pzd;           // nwg x nsplit x 2 x 64
+    uint32_t* cnt;         // nwg tickets, zero between launches
 };
 
 struct PassArgs {
@@ -77,7 +88,6 @@ struct PassArgs {
     double zeta;           // threshold zeta_{k+1}
     float zeta_f;          // largest float <= zeta (exact float comparison)
     int32_t err_mode;
-    int32_t segmax;        // rows per wave per LDS stage (set by the launcher)
     const DevState* st;
 };
 
@@ -254,6 +264,10 @@ hipError_t launch_svd_batch(const SvdArgs* arr_dev, int nb, int G, int P, size_t
 hipError_t launch_svdl(const SvdArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_svdl_batch(const SvdArgs* arr_dev, int nb, int G, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
+// Row blocks per column tile for a pass side with s rows (1: no split), and
+// the partial-sum bytes per (tile, block) that a split needs.
+int pass_nsplit(int dtype, int R, int s, int tiles);
+size_t pass_split_bytes(int dtype, int R);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
 size_t svd_lds_bytes(int sJ, int bs16, int P);
@@ -267,13 +281,12 @@ hipError_t launch_alg2(const Alg2Args& a, hipStream_t s);
 // unrolled mode
 hipError_t launch_ucore(const CoreArgs* arr, const int32_t* off, int nb, int total_blocks, const double* zk,
                         double tau_rel, int dtype, int R, hipStream_t s);
-hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total_blocks, int max_s,
-                        const double* zk, double tau_rel, int dtype, int R, hipStream_t s);
-int upass_segmax(int dtype, int R);
+hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total_blocks,
+                        const double* zeta_k, double tau_rel, int dtype, int R, hipStream_t s);
 hipError_t launch_uloss(const ULoss* arr, const int32_t* off, int nb, int total_blocks, int dtype, hipStream_t s);
 hipError_t launch_ulossadj(const ULoss* arr, const int32_t* off, int nb, int total_blocks, const double* dloss,
                            int dtype, hipStream_t s);
-hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total_blocks,
+hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total_blocks, int max_s,
                          const double* zk, double tau_rel, int dtype, int R, hipStream_t s);
 hipError_t launch_ubsmall(const UBack* arr, int nb, int max_s16, int cg_max_it, double cg_tol, hipStream_t s);
 hipError_t launch_ubreduce(const UBack* arr, const int32_t* off, int nb, int total_blocks, int dtype, hipStream_t s);

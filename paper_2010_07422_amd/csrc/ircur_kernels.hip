@@ -108,13 +108,17 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
     if (a.st->stop) return;
     __shared__ F red[PassTree<T, F, R>::nred];
     __shared__ double redzd[PassTree<T, F, R>::nzd];
-    extern __shared__ __align__(16) unsigned char dyn[];
-    F* qstage = (F*)dyn;
-    const int wg = blockIdx.x;
-    if (wg < a.side[0].nwg)
-        side_body<T, F, R, LIT>(a.side[0], wg, a.zeta, a.zeta_f, red, redzd, qstage, a.segmax);
-    else
-        side_body<T, F, R, LIT>(a.side[1], wg - a.side[0].nwg, a.zeta, a.zeta_f, red, redzd, qstage, a.segmax);
+    // block -> (side, column tile, row block); the row blocks of a tile are adjacent
+    const int b = blockIdx.x;
+    const int ns0 = a.side[0].nsplit > 1 ? a.side[0].nsplit : 1;
+    const int ns1 = a.side[1].nsplit > 1 ? a.side[1].nsplit : 1;
+    const int nb0 = a.side[0].nwg * ns0;
+    if (b < nb0) {
+        side_body<T, F, R, LIT>(a.side[0], b / ns0, b % ns0, a.zeta, a.zeta_f, red, redzd);
+    } else {
+        const int bb = b - nb0;
+        side_body<T, F, R, LIT>(a.side[1], bb / ns1, bb % ns1, a.zeta, a.zeta_f, red, redzd);
+    }
 }
 
 // ------------------------------------------------------------- finalize ---
@@ -171,28 +175,11 @@ static hipError_t core_r(const CoreArgs& a, hipStream_t s) {
 }
 
 template <typename T, typename F, int R>
-static hipError_t pass_r(const PassArgs& a0, hipStream_t s) {
-    PassArgs a = a0;
-    constexpr int U = RowsInFlight<T>::value;
-    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
-    const int budget = pass_stage_budget(PassTree<T, F, R>::bytes);
-    int segmax = (budget / (PassWaves<T, R>::value * rowbytes)) / U * U;
-    if (segmax < U) segmax = U;
-    const int chunk = (std::max(a.side[0].s, a.side[1].s) + PassWaves<T, R>::value - 1) / PassWaves<T, R>::value;
-    const int seg = chunk <= segmax ? chunk : segmax;
-    a.segmax = segmax;
-    const size_t lds = (size_t)PassWaves<T, R>::value * seg * rowbytes;
-    static bool attr[2] = {false, false};
-    const int li = a.err_mode == 0 ? 0 : 1;
-    const void* fn = a.err_mode == 0 ? (const void*)pass_kernel<T, F, R, true> : (const void*)pass_kernel<T, F, R, false>;
-    if (!attr[li]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, budget);
-        if (e != hipSuccess) return e;
-        attr[li] = true;
-    }
-    const unsigned grid = (unsigned)(a.side[0].nwg + a.side[1].nwg);
-    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 64 * PassWaves<T, R>::value, lds, s>>>(a);
-    else pass_kernel<T, F, R, false><<<grid, 64 * PassWaves<T, R>::value, lds, s>>>(a);
+static hipError_t pass_r(const PassArgs& a, hipStream_t s) {
+    const unsigned grid = (unsigned)(a.side[0].nwg * std::max(1, a.side[0].nsplit) +
+                                     a.side[1].nwg * std::max(1, a.side[1].nsplit));
+    if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
+    else pass_kernel<T, F, R, false><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -208,6 +195,28 @@ hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s) {
     if (dtype == 1) { IRCUR_RANK_SWITCH(pass_r, float, float, R, a, s) }
     if (dtype == 2) { IRCUR_RANK_SWITCH(pass_r, bf16_t, float, R, a, s) }
     return hipErrorInvalidValue;
+}
+
+template <typename T, typename F, int R>
+static int nsplit_r(int s, int tiles) {
+    // blocks of about kPassSplitRows rows, at most 2048 workgroups per side
+    int ns = (s + kPassSplitRows - 1) / kPassSplitRows;
+    ns = std::min(ns, std::max(1, 2048 / std::max(tiles, 1)));
+    ns = std::min(ns, kPassMaxSplit);
+    return std::max(ns, 1);
+}
+
+int pass_nsplit(int dtype, int R, int s, int tiles) {
+    if (dtype == 0) { IRCUR_RANK_SWITCH(nsplit_r, double, double, R, s, tiles) }
+    if (dtype == 1) { IRCUR_RANK_SWITCH(nsplit_r, float, float, R, s, tiles) }
+    if (dtype == 2) { IRCUR_RANK_SWITCH(nsplit_r, bf16_t, float, R, s, tiles) }
+    return 1;
+}
+
+size_t pass_split_bytes(int dtype, int R) {
+    const size_t f = dtype == 0 ? sizeof(double) : sizeof(float);
+    const size_t V = dtype == 2 ? ColsPerLane<bf16_t>::value : 1;
+    return (size_t)R * V * 64 * f + 128 * sizeof(double);
 }
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {

@@ -110,7 +110,6 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void upass_kernel(co
                                                                const double* __restrict__ zk, double tau_rel) {
     __shared__ F red[PassTree<T, F, R>::nred];
     __shared__ double redzd[PassTree<T, F, R>::nzd];
-    extern __shared__ __align__(16) unsigned char dyn[];
     const int b = find_inst(off, nb, blockIdx.x);
     const PassArgs& a = arr[b];
     const int local = blockIdx.x - off[b];
@@ -118,10 +117,9 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void upass_kernel(co
     const float zf = round_down_f(zeta);
     const F tz = (F)(tau_rel * zeta);
     if (local < a.side[0].nwg)
-        side_body<T, F, R, false, GATE>(a.side[0], local, zeta, zf, red, redzd, (F*)dyn, a.segmax, tz);
+        side_body<T, F, R, false, GATE>(a.side[0], local, 0, zeta, zf, red, redzd, tz);
     else
-        side_body<T, F, R, false, GATE>(a.side[1], local - a.side[0].nwg, zeta, zf, red, redzd, (F*)dyn,
-                                        a.segmax, tz);
+        side_body<T, F, R, false, GATE>(a.side[1], local - a.side[0].nwg, 0, zeta, zf, red, redzd, tz);
 }
 
 // ---------------------------------------------------------------- loss ---
@@ -256,11 +254,50 @@ __global__ __launch_bounds__(256) void ulossadj_kernel(const ULoss* __restrict__
 //     Bbar_k[:, j] = -sum_a A_k[I_a, :]^T Xbar (dense),  Abar_k[I_a, :] partial -sum_j Xbar B_k[:, j]^T
 // and the column side with Cbar[i, b] = Abar[i, :] Tp[b, :] and the roles of
 // the factors exchanged.
+constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2); }
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Sum over the 64 lanes of V values per lane at once (V a power of two, at most
+// 64), by recursive halving: at distance d a lane keeps one half of its values
+// (the upper half if bit d of its lane id is set) and adds the partner's copy
+// of that half. After log2 V exchanges lane l holds the whole sum of value
+// l >> (6 - log2 V); plain butterfly steps finish the remaining distances.
+// V - 1 exchanges in all instead of 6 V; the summation tree is fixed.
+template <int CNT, int D, int V, typename F>
+struct HalvingLevel {
+    static __device__ __forceinline__ void run(F (&a)[V], int lane) {
+        constexpr int h = CNT / 2;
+        const bool hi = (lane & D) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const F send = hi ? a[j] : a[j + h];
+            const F keep = hi ? a[j + h] : a[j];
+            a[j] = keep + __shfl_xor(send, D, 64);
+        }
+        HalvingLevel<h, D / 2, V, F>::run(a, lane);
+    }
+};
+template <int D, int V, typename F>
+struct HalvingLevel<1, D, V, F> {
+    static __device__ __forceinline__ void run(F (&)[V], int) {}
+};
+
+template <int V, typename F>
+__device__ __forceinline__ F halving_sum(F (&a)[V], int lane) {
+    static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two <= 64");
+    HalvingLevel<V, 32, V, F>::run(a, lane);
+    F v = a[0];
+#pragma unroll
+    for (int d = 32 >> ilog2(V); d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
 template <typename T, typename F, int R, bool GATE, int PH>
 __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ arr, const int32_t* __restrict__ off,
                                                      int nb, const double* __restrict__ zk, double tau_rel) {
     __shared__ F red[4][R][64];
     __shared__ double zred[4];
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int b = find_inst(off, nb, blockIdx.x);
     const UBack& u = arr[b];
     const int local = blockIdx.x - off[b];
@@ -268,8 +305,9 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     const float zf = round_down_f(zeta);
     const F zF = (F)zeta;
     const F tz = (F)(tau_rel * zeta);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const bool rowside = local < u.nwg_row;
     const int wg = rowside ? local : local - u.nwg_row;
     const int64_t n = rowside ? u.n2 : u.n1;
@@ -287,6 +325,44 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     const F* __restrict__ Qf = rowside ? At : Bk;
     const int64_t nq = rowside ? u.n1 : u.n2;
     double* __restrict__ part = rowside ? u.partI : u.partJ;
+
+    // per-row data in LDS: the row index, the factor row q (R values) and, in
+    // phase 2, Wt, X1, W_r (row side) or Tp (column side) of that row
+    const int nxv = PH == 2 ? (rowside ? 3 * R : R) : 0;
+    const int stride = R + nxv;
+    int* rix = (int*)dyn;                                         // s ints
+    F* qs = (F*)(dyn + (((size_t)s * sizeof(int) + 15) & ~(size_t)15));
+    for (int e = tid; e < s; e += 256) rix[e] = rows[e];
+    __syncthreads();
+    {
+        const int tot = s * stride;
+        for (int base = tid; base < tot; base += 256 * 8) {
+            F v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = base + q * 256;
+                F x = F(0);
+                if (e < tot) {
+                    const int a = e / stride, c = e - a * stride;
+                    if (c < R) {
+                        x = Qf[c * nq + rix[a]];
+                    } else if (PH == 2) {
+                        const int k = c - R, which = k / R, cr = k - which * R;
+                        const double* srcd = rowside ? (which == 0 ? u.Wt : (which == 1 ? u.X1 : u.Wr)) : u.Tp;
+                        x = (F)srcd[(int64_t)a * R + cr];
+                    }
+                }
+                v[q] = x;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = base + q * 256;
+                if (e < tot) qs[e] = v[q];
+            }
+        }
+    }
+    __syncthreads();
+
     F p[R], pb[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
@@ -311,22 +387,27 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     const int chunk = (s + 3) >> 2;
     const int a_begin = wave * chunk;
     const int a_end = min(s, a_begin + chunk);
-    constexpr int U = 4;
+    constexpr int U = 8;
+    F nx[U];
+    if (a_end > a_begin) {
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) nx[uu] = ld<T, F>(X + (int64_t)rix[min(a_begin + uu, a_end - 1)] * ldX + cc);
+    }
     for (int a0 = a_begin; a0 < a_end; a0 += U) {
         F dv[U];
 #pragma unroll
-        for (int uu = 0; uu < U; ++uu) {
-            const int a = min(a0 + uu, a_end - 1);
-            dv[uu] = ld<T, F>(X + (int64_t)rows[a] * ldX + cc);
+        for (int uu = 0; uu < U; ++uu) dv[uu] = nx[uu];
+        if (a0 + U < a_end) {
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu) nx[uu] = ld<T, F>(X + (int64_t)rix[min(a0 + U + uu, a_end - 1)] * ldX + cc);
         }
+        F wv[U];    // per row: the value whose products with the column factors are summed
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int a = a0 + uu;
+            wv[uu] = F(0);
             if (a < a_end) {
-                const int64_t rix = rows[a];
-                F q[R];
-#pragma unroll
-                for (int c = 0; c < R; ++c) q[c] = Qf[c * nq + rix];
+                const F* q = qs + (size_t)a * stride;
                 const F d = valid ? dv[uu] : F(0);
                 F dot = F(0);
 #pragma unroll
@@ -342,40 +423,54 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                 }
                 if (PH == 1) {
                     const F v = GATE ? d - x * g : (g != F(0) ? d - x : d);
-#pragma unroll
-                    for (int c = 0; c < R; ++c) {
-                        double sc = valid ? (double)v * (double)pb[c] : 0.0;
-                        sc = wave_sum(sc);
-                        if (lane == 0) part[((int64_t)wg * s + a) * R + c] = sc;
-                    }
+                    wv[uu] = valid ? v : F(0);
                 } else {
                     F ybar = F(0);
                     if (rowside) {
 #pragma unroll
-                        for (int c = 0; c < R; ++c) ybar = fmaT((F)u.Wt[(int64_t)a * R + c], pb[c], ybar);
+                        for (int c = 0; c < R; ++c) ybar = fmaT(q[R + c], pb[c], ybar);
                         if (inJ) {
 #pragma unroll
                             for (int c = 0; c < R; ++c) {
-                                ybar = fmaT((F)u.X1[(int64_t)a * R + c], vb[c], ybar);
-                                ybar = fmaT((F)u.Wr[(int64_t)a * R + c], xb[c], ybar);
+                                ybar = fmaT(q[2 * R + c], vb[c], ybar);
+                                ybar = fmaT(q[3 * R + c], xb[c], ybar);
                             }
                         }
                     } else {
 #pragma unroll
-                        for (int c = 0; c < R; ++c) ybar = fmaT(pb[c], (F)u.Tp[(int64_t)a * R + c], ybar);
+                        for (int c = 0; c < R; ++c) ybar = fmaT(pb[c], q[R + c], ybar);
                     }
                     const F xbar = -ybar * dSdx;
                     if (valid) zacc += -(double)ybar * (double)dSdz;
 #pragma unroll
                     for (int c = 0; c < R; ++c) acc[c] = fmaT(q[c], xbar, acc[c]);
-#pragma unroll
-                    for (int c = 0; c < R; ++c) {
-                        double sc = valid ? (double)xbar * (double)p[c] : 0.0;
-                        sc = wave_sum(sc);
-                        if (lane == 0) part[((int64_t)wg * s + a) * R + c] = -sc;
-                    }
+                    wv[uu] = valid ? xbar : F(0);
                 }
             }
+        }
+        // part[row][c] = sum over the 64 columns of wv * m[c] (m = Bbar resp. P),
+        // RG rows at a time by recursive halving
+        constexpr int RP = pow2_ceil(R);
+        constexpr int VMAX = sizeof(F) == 8 ? 32 : 64;
+        constexpr int RG = U * RP <= VMAX ? U : VMAX / RP;
+        constexpr int V = RG * RP;
+        constexpr int SH = 6 - ilog2(V);
+#pragma unroll
+        for (int g0 = 0; g0 < U; g0 += RG) {
+            F hv[V];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+#pragma unroll
+                for (int c = 0; c < RP; ++c) {
+                    if (c < R) hv[i * RP + c] = wv[g0 + i] * (PH == 1 ? pb[c] : p[c]);
+                    else hv[i * RP + c] = F(0);
+                }
+            }
+            const F sum = halving_sum<V>(hv, lane);
+            const int idx = lane >> SH;
+            const int row = a0 + g0 + idx / RP, c = idx % RP;
+            if ((lane & ((1 << SH) - 1)) == 0 && c < R && row < a_end)
+                part[((int64_t)wg * s + row) * R + c] = PH == 1 ? (double)sum : -(double)sum;
         }
     }
     if (PH == 2) {
@@ -774,45 +869,34 @@ hipError_t ucore_r(const CoreArgs* arr, const int32_t* off, int nb, int total, c
 }
 
 template <typename T, typename F, int R>
-int upass_segmax_r() {
-    constexpr int U = RowsInFlight<T>::value;
-    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
-    const int segmax = (pass_stage_budget(PassTree<T, F, R>::bytes) / (PassWaves<T, R>::value * rowbytes)) / U * U;
-    return segmax < U ? U : segmax;
-}
-
-template <typename T, typename F, int R>
-hipError_t upass_r(const PassArgs* arr, const int32_t* off, int nb, int total, int max_s, const double* zk,
-                   double tau, hipStream_t s) {
-    constexpr int U = RowsInFlight<T>::value;
-    constexpr int rowbytes = RowStride<F, R>::value * (int)sizeof(F);
-    const int budget = pass_stage_budget(PassTree<T, F, R>::bytes);
-    const int segmax = upass_segmax_r<T, F, R>();
-    const int chunk = (max_s + PassWaves<T, R>::value - 1) / PassWaves<T, R>::value;
-    const int seg = chunk <= segmax ? chunk : segmax;
-    const size_t lds = (size_t)PassWaves<T, R>::value * seg * rowbytes;
-    static bool attr[2] = {false, false};
-    const int gi = tau > 0.0 ? 1 : 0;
-    const void* fn = tau > 0.0 ? (const void*)upass_kernel<T, F, R, true> : (const void*)upass_kernel<T, F, R, false>;
-    if (!attr[gi]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, budget);
-        if (e != hipSuccess) return e;
-        attr[gi] = true;
-    }
-    if (tau > 0.0) upass_kernel<T, F, R, true><<<total, 64 * PassWaves<T, R>::value, lds, s>>>(arr, off, nb, zk, tau);
-    else upass_kernel<T, F, R, false><<<total, 64 * PassWaves<T, R>::value, lds, s>>>(arr, off, nb, zk, tau);
+hipError_t upass_r(const PassArgs* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
+                   hipStream_t s) {
+    if (tau > 0.0) upass_kernel<T, F, R, true><<<total, 64 * PassWaves<T, R>::value, 0, s>>>(arr, off, nb, zk, tau);
+    else upass_kernel<T, F, R, false><<<total, 64 * PassWaves<T, R>::value, 0, s>>>(arr, off, nb, zk, tau);
     return hipGetLastError();
 }
 
 template <typename T, typename F, int R>
-hipError_t ubpass_r(int phase, const UBack* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
-                    hipStream_t s) {
+hipError_t ubpass_r(int phase, const UBack* arr, const int32_t* off, int nb, int total, int max_s, const double* zk,
+                    double tau, hipStream_t s) {
+    const size_t lds = (((size_t)max_s * sizeof(int) + 15) & ~(size_t)15) + (size_t)max_s * 4 * R * sizeof(F);
+    const size_t stat = sizeof(F) * 4 * R * 64 + 4 * sizeof(double);      // the reduction arrays
+    if (lds + stat > 160 * 1024) return hipErrorInvalidValue;
+    const void* fns[4] = {(const void*)ubpass_kernel<T, F, R, false, 1>, (const void*)ubpass_kernel<T, F, R, true, 1>,
+                          (const void*)ubpass_kernel<T, F, R, false, 2>, (const void*)ubpass_kernel<T, F, R, true, 2>};
+    static size_t granted[4] = {0, 0, 0, 0};
+    const int fi = (phase == 1 ? 0 : 2) + (tau > 0.0 ? 1 : 0);
+    if (lds > 64 * 1024 && lds > granted[fi]) {
+        hipError_t e = hipFuncSetAttribute(fns[fi], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        granted[fi] = lds;
+    }
     if (phase == 1) {
-        if (tau > 0.0) ubpass_kernel<T, F, R, true, 1><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
-        else ubpass_kernel<T, F, R, false, 1><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+        if (tau > 0.0) ubpass_kernel<T, F, R, true, 1><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
+        else ubpass_kernel<T, F, R, false, 1><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
     } else {
-        if (tau > 0.0) ubpass_kernel<T, F, R, true, 2><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
-        else ubpass_kernel<T, F, R, false, 2><<<total, 256, 0, s>>>(arr, off, nb, zk, tau);
+        if (tau > 0.0) ubpass_kernel<T, F, R, true, 2><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
+        else ubpass_kernel<T, F, R, false, 2><<<total, 256, lds, s>>>(arr, off, nb, zk, tau);
     }
     return hipGetLastError();
 }
@@ -832,9 +916,6 @@ hipError_t ubpass_r(int phase, const UBack* arr, const int32_t* off, int nb, int
         default: return hipErrorInvalidValue;                   \
     }
 
-template <typename T, typename F, int R>
-int useg_r() { return upass_segmax_r<T, F, R>(); }
-
 }  // namespace
 
 hipError_t launch_ucore(const CoreArgs* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
@@ -844,19 +925,11 @@ hipError_t launch_ucore(const CoreArgs* arr, const int32_t* off, int nb, int tot
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total, int max_s, const double* zk,
-                        double tau, int dtype, int R, hipStream_t s) {
-    if (dtype == 0) { IRCUR_URANK_SWITCH(upass_r, double, double, R, arr, off, nb, total, max_s, zk, tau, s) }
-    if (dtype == 1) { IRCUR_URANK_SWITCH(upass_r, float, float, R, arr, off, nb, total, max_s, zk, tau, s) }
+hipError_t launch_upass(const PassArgs* arr, const int32_t* off, int nb, int total, const double* zk, double tau,
+                        int dtype, int R, hipStream_t s) {
+    if (dtype == 0) { IRCUR_URANK_SWITCH(upass_r, double, double, R, arr, off, nb, total, zk, tau, s) }
+    if (dtype == 1) { IRCUR_URANK_SWITCH(upass_r, float, float, R, arr, off, nb, total, zk, tau, s) }
     return hipErrorInvalidValue;
-}
-
-int upass_segmax(int dtype, int R) {
-    auto f = [&]() -> int {
-        if (dtype == 0) { IRCUR_URANK_SWITCH(useg_r, double, double, R) }
-        IRCUR_URANK_SWITCH(useg_r, float, float, R)
-    };
-    return f();
 }
 
 hipError_t launch_uloss(const ULoss* arr, const int32_t* off, int nb, int total, int dtype, hipStream_t s) {
@@ -873,10 +946,10 @@ hipError_t launch_ulossadj(const ULoss* arr, const int32_t* off, int nb, int tot
     return hipGetLastError();
 }
 
-hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total, const double* zk,
-                         double tau, int dtype, int R, hipStream_t s) {
-    if (dtype == 0) { IRCUR_URANK_SWITCH(ubpass_r, double, double, R, phase, arr, off, nb, total, zk, tau, s) }
-    if (dtype == 1) { IRCUR_URANK_SWITCH(ubpass_r, float, float, R, phase, arr, off, nb, total, zk, tau, s) }
+hipError_t launch_ubpass(int phase, const UBack* arr, const int32_t* off, int nb, int total, int max_s,
+                         const double* zk, double tau, int dtype, int R, hipStream_t s) {
+    if (dtype == 0) { IRCUR_URANK_SWITCH(ubpass_r, double, double, R, phase, arr, off, nb, total, max_s, zk, tau, s) }
+    if (dtype == 1) { IRCUR_URANK_SWITCH(ubpass_r, float, float, R, phase, arr, off, nb, total, max_s, zk, tau, s) }
     return hipErrorInvalidValue;
 }
 

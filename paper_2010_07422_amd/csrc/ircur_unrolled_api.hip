@@ -83,7 +83,7 @@ struct ircur_unrolled {
     double tau_rel = 0.0;
     size_t fsz = 8, esz = 8;
     hipStream_t stream = nullptr;
-    int G = 1, max_s = 0, max_sI16 = 0, max_sJ16 = 0, max_bs16 = 0, segmax = 0;
+    int G = 1, max_s = 0, max_sI16 = 0, max_sJ16 = 0, max_bs16 = 0;
     size_t svd_lds = 0;
     std::vector<UHost> inst;
     void* common = nullptr;      // argument tables, offsets, small shared arrays
@@ -206,7 +206,6 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
         if (!ok || (size_t)u->G * nb > 256) { delete u; return IRCUR_ERR_UNSUPPORTED; }
     }
     if (ubsmall_lds_bytes(std::max(u->max_sI16, u->max_sJ16)) > 160 * 1024) { delete u; return IRCUR_ERR_UNSUPPORTED; }
-    u->segmax = upass_segmax(dtype, R);
 
 #define UTRY(x)                                     \
     do {                                            \
@@ -403,7 +402,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             r1.X = in.Dt; r1.ldX = in.ldDt; r1.rows = Jk; r1.s = sJ; r1.n = in.n1; r1.P = At_k;
             r1.rowdata = h.rowJ; r1.Gm = h.GmJ; r1.outmat = h.scaleJ; r1.out = At_k1;
             r1.part = h.epart + 2 * h.nwg_row; r1.nwg = h.nwg_col;
-            pa.err_mode = 1; pa.segmax = u->segmax; pa.st = st;
+            pa.err_mode = 1; pa.st = st;
 
             UBack& ub = back[e];
             ub.D = in.D; ub.ldD = in.ldD; ub.Dt = in.Dt; ub.ldDt = in.ldDt; ub.n1 = in.n1; ub.n2 = in.n2;
@@ -457,7 +456,7 @@ int ircur_unrolled_forward(ircur_unrolled* u, const double* zeta_dev, double* lo
         UCHK(u, launch_ucore(u->d_core + e, u->off_core, nb, u->tot_core, u->zeta + k, u->tau_rel, u->dtype, R,
                              u->stream));
         UCHK(u, launch_svdl_batch(u->d_svd + e, nb, u->G, u->svd_lds, u->stream));
-        UCHK(u, launch_upass(u->d_pass + e, u->off_pass, nb, u->tot_pass, u->max_s, u->zeta + k, u->tau_rel,
+        UCHK(u, launch_upass(u->d_pass + e, u->off_pass, nb, u->tot_pass, u->zeta + k, u->tau_rel,
                              u->dtype, R, u->stream));
     }
     UCHK(u, launch_uloss(u->d_loss, u->off_gram, nb, u->tot_gram, u->dtype, u->stream));
@@ -478,9 +477,9 @@ int ircur_backward(ircur_unrolled* u, const double* dloss_dev, double* dzeta_dev
     for (int k = u->K - 1; k >= 0; --k) {
         const UBack* arr = u->d_back + (size_t)k * nb;
         const double* zk = u->zeta + k;        // the forward pass's threshold of this step
-        UCHK(u, launch_ubpass(1, arr, u->off_pass, nb, u->tot_pass, zk, u->tau_rel, u->dtype, R, u->stream));
+        UCHK(u, launch_ubpass(1, arr, u->off_pass, nb, u->tot_pass, u->max_s, zk, u->tau_rel, u->dtype, R, u->stream));
         UCHK(u, launch_ubsmall(arr, nb, s16, 400, cg_tol, u->stream));
-        UCHK(u, launch_ubpass(2, arr, u->off_pass, nb, u->tot_pass, zk, u->tau_rel, u->dtype, R, u->stream));
+        UCHK(u, launch_ubpass(2, arr, u->off_pass, nb, u->tot_pass, u->max_s, zk, u->tau_rel, u->dtype, R, u->stream));
         UCHK(u, launch_ubreduce(arr, u->off_bred, nb, u->tot_bred, u->dtype, u->stream));
     }
     UCHK(u, launch_udzeta(u->dz_inst, nb, u->K, dzeta_dev, u->stream));

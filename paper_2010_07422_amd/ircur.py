@@ -72,6 +72,7 @@ _SIGS = {
     "ircur_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "ircur_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ircur_get_timing": (ctypes.c_int, [_P, _DP, ctypes.POINTER(ctypes.c_int64)]),
+    "ircur_time_pass": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),
     "ircur_get_info": (ctypes.c_int, [_P, _I32P, _DP, _DP, _I32P]),
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
@@ -340,6 +341,13 @@ class IRCUR:
         cnt = ctypes.c_int64()
         self._check(lib().ircur_get_timing(self.h, ms, ctypes.byref(cnt)), "ircur_get_timing")
         return list(ms), cnt.value
+
+    def time_pass(self, reps=200):
+        """Mean duration in microseconds of the last iteration's pass kernel,
+        launched `reps` times back to back between two HIP events."""
+        us = ctypes.c_double()
+        self._check(lib().ircur_time_pass(self.h, int(reps), ctypes.byref(us)), "ircur_time_pass")
+        return us.value
 
     def phase_profile(self):
         buf = (ctypes.c_double * 16)()

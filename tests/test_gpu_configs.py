@@ -212,3 +212,32 @@ def test_repeat_is_bitwise_and_modes():
     ref = O.ircur(p.D, 3, 70, 75, p.Lmax, 0.7, -1.0, 6, seed=4, resample=True, err_mode=1)
     assert np.allclose(ctx.history(), ref.e_hist, rtol=1e-6)
     ctx.close()
+
+
+def test_time_pass_leaves_the_run_unchanged():
+    torch = require_gpu()
+    from paper_2010_07422_amd.ircur import IrcurError, ERR_STATE
+    p = synth.planted(700, 650, 3, 0.1, seed=21)
+    kw = dict(eps=-1.0, max_iter=20, seed=2, resample=True)
+    print("case time_pass", flush=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float32, 3, 80, 75, p.Lmax, **kw)
+    with pytest.raises(IrcurError) as ei:
+        ctx.time_pass(3)
+    assert ei.value.code == ERR_STATE
+    ctx.enqueue(6)
+    ctx.sync()
+    A0, B0 = factors_np(ctx)
+    us = ctx.time_pass(20)
+    A1, B1 = factors_np(ctx)
+    assert us > 0.0 and np.array_equal(A0, A1) and np.array_equal(B0, B1)
+    ctx.enqueue(6)
+    ctx.sync()
+    A1, B1 = factors_np(ctx)
+    ctx2, _ = _ctx(torch, Dd, None, 3, 80, 75, p.Lmax, **kw)
+    ctx2.enqueue(12)
+    ctx2.sync()
+    A2, B2 = factors_np(ctx2)
+    assert np.array_equal(A1, A2) and np.array_equal(B1, B2)
+    assert ctx.history() == ctx2.history()
+    ctx.close()
+    ctx2.close()
