@@ -29,6 +29,42 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 
 
+# HBM traffic of the pass kernel measured with rocprofv3 (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by a plain device copy); valid only while the
+# sources that define the kernel and its launch are the ones measured.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_kernel_n10000_r10_traffic.md")
+PASS_SOURCES = ("paper_2010_07422_amd/csrc/ircur_kernels.hip", "paper_2010_07422_amd/csrc/ircur_device.h",
+                "paper_2010_07422_amd/csrc/ircur_internal.h", "paper_2010_07422_amd/csrc/ircur_capi.hip")
+
+
+def pass_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype):
+    """Bytes per launch of the pass kernel from the committed counter summary,
+    or None when the kernel's sources have changed since it was taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != pass_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_{dtype}")
+    return int(v) if v else None
+
+
 def pass_bytes(n1, n2, sI, sJ, r, b_d, b_f):
     """Algorithmic HBM bytes of one pass launch: the sampled rows of D and of
     D^T, the factors read (B_k, A_k^T) and written (B_{k+1}, A_{k+1}^T)."""
@@ -218,6 +254,7 @@ def main():
         extra["f64"] = {k: res64[k] for k in ("iters_per_s", "ms_per_step", "pass_us", "kernel_us",
                                                "time_to_1e-5_ms", "iters_to_1e-5")}
         extra["f64"]["pass_GBs"] = pass_bytes(n, n, s, s, r, 8, 8) / (res64["pass_us"] * 1e3)
+        extra["f64"]["pass_traffic_bytes"] = measured_traffic("f64")
         extra["bf16_vs_f64_rel_L"] = O.factored_rel_diff(A_bf, B_bf, A64, B64)
     extra["bf16_vs_truth_rel_L"] = O.factored_rel_diff(A_bf, B_bf, p.W, p.V.T)
     nbytes = pass_bytes(n, n, s, s, r, 2, 4)
@@ -241,7 +278,7 @@ def main():
                    "n": n, "r": r, "alpha": alpha, "sI": s, "sJ": s},
         "roofline": {"kernel": "pass (fused row/column pass)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("bf16"),
                      "bytes_per_launch": nbytes, "avg_launch_us": round(pass_us, 3)},
         "time_to_1e-5_ms": round(res["time_to_1e-5_ms"], 3),
         "iters_to_1e-5": res["iters_to_1e-5"],

@@ -613,10 +613,12 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         c->Dt = Dt_dev;
         c->ldDt = ldDt;
     } else {
-        TRY(dalloc_bytes(c, &c->Dt_own, (size_t)p.n1 * p.n2 * c->esz));
+        // rows of D^T start on 128-byte boundaries (whole cache lines per column tile)
+        const int64_t al = 128 / (int64_t)c->esz;
+        c->ldDt = (p.n1 + al - 1) / al * al;
+        TRY(dalloc_bytes(c, &c->Dt_own, (size_t)c->ldDt * p.n2 * c->esz));
         c->Dt = c->Dt_own;
-        c->ldDt = p.n1;
-        hipError_t e = launch_transpose(D_dev, p.ldD, c->Dt_own, p.n1, p.n1, p.n2, (int)c->esz, c->stream);
+        hipError_t e = launch_transpose(D_dev, p.ldD, c->Dt_own, c->ldDt, p.n1, p.n2, (int)c->esz, c->stream);
         if (e != hipSuccess) { free_all(c); delete c; return IRCUR_ERR_DEVICE; }
     }
     TRY(reset_state(c));

@@ -26,8 +26,8 @@ inline int row_stride(int R, int fsz) { return ((3 * R * fsz + 15) / 16) * (16 /
 // column tile.
 constexpr int kPassSplitRows = 128;
 constexpr int kPassMaxSplit = 64;
-// Output columns of one pass workgroup (64 lanes, one column each).
-constexpr int pass_cols(int) { return 64; }
+// Output columns of one pass column tile (64 lanes x the columns per lane).
+int pass_cols(int dtype);
 
 inline int pad_rank(int r) {
     for (int v : kRanks) if (v >= r) return v;

@@ -108,11 +108,17 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
     if (a.st->stop) return;
     __shared__ F red[PassTree<T, F, R>::nred];
     __shared__ double redzd[PassTree<T, F, R>::nzd];
-    // block -> (side, column tile, row block); the row blocks of a tile are adjacent
-    const int b = blockIdx.x;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so work item
+    // w = xcd * per + slot gives each XCD a contiguous range of (side, column
+    // tile, row block) items: neighbouring tiles, which share the cache lines at
+    // their edges, and the row blocks of one tile meet in the same L2
     const int ns0 = a.side[0].nsplit > 1 ? a.side[0].nsplit : 1;
     const int ns1 = a.side[1].nsplit > 1 ? a.side[1].nsplit : 1;
     const int nb0 = a.side[0].nwg * ns0;
+    const int nbt = nb0 + a.side[1].nwg * ns1;
+    const int per = (int)(gridDim.x >> 3);
+    const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (b >= nbt) return;
     if (b < nb0) {
         side_body<T, F, R, LIT>(a.side[0], b / ns0, b % ns0, a.zeta, a.zeta_f, red, redzd);
     } else {
@@ -176,8 +182,9 @@ static hipError_t core_r(const CoreArgs& a, hipStream_t s) {
 
 template <typename T, typename F, int R>
 static hipError_t pass_r(const PassArgs& a, hipStream_t s) {
-    const unsigned grid = (unsigned)(a.side[0].nwg * std::max(1, a.side[0].nsplit) +
-                                     a.side[1].nwg * std::max(1, a.side[1].nsplit));
+    const unsigned nb = (unsigned)(a.side[0].nwg * std::max(1, a.side[0].nsplit) +
+                                   a.side[1].nwg * std::max(1, a.side[1].nsplit));
+    const unsigned grid = (nb + 7) / 8 * 8;          // a whole number of rounds over the 8 XCDs
     if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
     else pass_kernel<T, F, R, false><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
     return hipGetLastError();
@@ -213,9 +220,14 @@ int pass_nsplit(int dtype, int R, int s, int tiles) {
     return 1;
 }
 
+int pass_cols(int dtype) {
+    return 64 * (dtype == 2 ? ColsPerLane<bf16_t>::value : (dtype == 1 ? ColsPerLane<float>::value
+                                                                       : ColsPerLane<double>::value));
+}
+
 size_t pass_split_bytes(int dtype, int R) {
     const size_t f = dtype == 0 ? sizeof(double) : sizeof(float);
-    const size_t V = dtype == 2 ? ColsPerLane<bf16_t>::value : 1;
+    const size_t V = pass_cols(dtype) / 64;
     return (size_t)R * V * 64 * f + 128 * sizeof(double);
 }
 
