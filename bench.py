@@ -56,8 +56,9 @@ def measured_traffic(dtype):
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_")):
-            k, v = line.strip().split(":", 1)
+        line = line.strip().lstrip("-").strip()
+        if ":" in line and line.startswith(("source_sha256", "traffic_bytes_")):
+            k, v = line.split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_sha256") != pass_source_hash():
         return None
