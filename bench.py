@@ -66,10 +66,7 @@ def measured_traffic(dtype):
     return int(v) if v else None
 
 
-def pass_bytes(n1, n2, sI, sJ, r, b_d, b_f):
-    """Algorithmic HBM bytes of one pass launch: the sampled rows of D and of
-    D^T, the factors read (B_k, A_k^T) and written (B_{k+1}, A_{k+1}^T)."""
-    return b_d * (sI * n2 + sJ * n1) + 2 * b_f * r * (n1 + n2)
+from paper_2010_07422_amd.sweeps import pass_bytes  # noqa: E402  (algorithmic bytes of one pass launch)
 
 
 def run_gpu(D, p, r, s, steps, warmup, label, pass_reps=1000):
@@ -220,6 +217,10 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-unrolled", action="store_true")
     ap.add_argument("--unrolled-steps", type=int, default=20)
+    ap.add_argument("--scaling", action="store_true",
+                    help="also run the size sweep n = 1000..30000 (IRCUR-R and -F, BF16) and k concurrent instances")
+    ap.add_argument("--phase", action="store_true",
+                    help="also run the recovery phase transition (n = 1000, r in {5, 10, 20}, 50 trials per cell)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of 256 MiB five times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -293,6 +294,14 @@ def main():
                                       "r=5, K=10, tau_rel=0.05, FP32)", **ur}
         if not args.no_cpu:
             line["unrolled"]["cpu_baseline"] = unrolled_cpu_baseline(ubatch, uzeta, 5, 0.05, args.cpu_budget)
+    if args.scaling:
+        from paper_2010_07422_amd import sweeps
+        line["scaling_sweep"] = sweeps.scaling_sweep()
+        line["concurrent_instances"] = sweeps.concurrent_throughput()
+    if args.phase:
+        from paper_2010_07422_amd import sweeps
+        rows, rate = sweeps.phase_transition()
+        line["phase_transition"] = {"trials_per_s": rate, "cells": rows}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, r, s, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -14,6 +14,9 @@ Workloads (all NumPy, float64 unless stated):
   columns): a rank-2 smooth background field times slowly varying per-frame
   gains, plus four rectangular blobs moving linearly.
 * ``unrolled_batch`` -- the ragged batch for the unrolled, differentiable mode.
+* ``planted_device`` -- the planted recipe drawn with torch on a device (for
+  sweeps at sizes where generating on the host is slow); same laws, its own
+  random stream.
 """
 from __future__ import annotations
 
@@ -155,3 +158,48 @@ CONFIGS = {
                                     eps=1e-5, max_iter=100, data_seed=3,
                                     index_seed=1, resample=True),
 }
+
+
+@dataclass
+class PlantedDevice:
+    D: "object"            # (n1, n2) torch tensor of the requested dtype
+    W: "object"            # (n1, r) float64, L = W @ V.T
+    V: "object"            # (n2, r) float64
+    nnz: int               # outliers drawn: round(alpha n1 n2)
+    Lmax: float            # max |L_ij|
+    mean_abs: float        # mean |L_ij|
+
+
+def planted_device(n1: int, n2: int, r: int, alpha: float, seed: int, device="cuda",
+                   dtype=None, outlier_scale: float = 10.0, row_block: int = 4096) -> PlantedDevice:
+    """The planted recipe of ``planted`` drawn with a seeded torch generator
+    on `device`: W, V i.i.d. N(0, 1); exactly round(alpha n1 n2) outlier
+    positions drawn without replacement; values uniform in +-outlier_scale
+    mean|L|.  L is formed in row blocks so that only D is held whole."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    W = torch.randn((n1, r), generator=g, device=device, dtype=torch.float64)
+    V = torch.randn((n2, r), generator=g, device=device, dtype=torch.float64)
+    D = torch.empty((n1, n2), device=device, dtype=dtype)
+    lmax, lsum = 0.0, 0.0
+    for i0 in range(0, n1, row_block):
+        Lb = W[i0:i0 + row_block] @ V.T
+        lmax = max(lmax, float(Lb.abs().max()))
+        lsum += float(Lb.abs().sum())
+        D[i0:i0 + row_block] = Lb.to(dtype)
+    mean_abs = lsum / (n1 * n2)
+    k = int(round(alpha * n1 * n2))
+    if k > 0:
+        pos = torch.randperm(n1 * n2, generator=g, device=device)[:k]
+        c = outlier_scale * mean_abs
+        vals = (torch.rand(k, generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0) * c
+        flat = D.view(-1)
+        for j0 in range(0, k, 1 << 26):
+            pj = pos[j0:j0 + (1 << 26)]
+            rows = torch.div(pj, n2, rounding_mode="floor")
+            Lv = (W[rows] * V[pj - rows * n2]).sum(1)
+            flat[pj] = (Lv + vals[j0:j0 + (1 << 26)]).to(dtype)
+        del pos, vals
+    return PlantedDevice(D=D, W=W, V=V, nnz=k, Lmax=lmax, mean_abs=mean_abs)
