@@ -220,7 +220,7 @@ def main():
     ap.add_argument("--scaling", action="store_true",
                     help="also run the size sweep n = 1000..30000 (IRCUR-R and -F, BF16) and k concurrent instances")
     ap.add_argument("--phase", action="store_true",
-                    help="also run the recovery phase transition (n = 1000, r in {5, 10, 20}, 50 trials per cell)")
+                    help="also run the recovery phase transition (n = 1000, r in {5, 10}, 50 trials per cell)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of 256 MiB five times (calibrates HBM counters)")
     args = ap.parse_args()

@@ -144,62 +144,90 @@ __device__ void mm_small(const double* A, int lda, const double* B, int ldb, dou
 
 // ------------------------------------------------ small factorisations ---
 // Cholesky G = L L^T of a P x P symmetric positive semidefinite matrix and
-// Linv = L^-1, by the first wave with lane i holding row i in registers.  A
-// pivot <= tol * max_j G_jj marks a dependent direction: its column of L and
-// row of Linv are zero and dead[j] = 1.  G, L, Linv are P x P in LDS.
+// Linv = L^-1, by the first wave with the P x P elements spread over its 64
+// lanes: lane l holds element (i, k) = (l / P + (64 / P) q, l % P) for
+// q < P * P / 64.  Step j of the factorisation forms column j of L in the
+// lanes that hold it and publishes it in LDS (in the order in which each lane
+// reads its rows); every lane then updates its trailing elements.  The inverse
+// (forward elimination on [L | I]) publishes each finished row the same way.
+// One wave: its LDS operations complete in program order, and a wave barrier
+// keeps the compiler from moving a lane's reads above the other lanes'
+// writes.  The only register reads across lanes are the P pivots, in uniform
+// control flow.  A pivot <= tol * max_j G_jj marks a dependent direction: its
+// column of L and row of Linv are zero and dead[j] = 1.  G, L, Linv are P x P
+// in LDS (L and Linv also serve as the exchange buffers).
 template <int P>
 __device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, double tol) {
+    static_assert(64 % P == 0 && P >= 8, "P must divide 64");
+    constexpr int RPL = 64 / P;          // rows covered by one q step
+    constexpr int NQ = P * P / 64;       // elements per lane
     if (threadIdx.x < 64) {
-        const int i = threadIdx.x;
-        double a[P];
+        const int l = threadIdx.x;
+        const int i0 = l / P, k = l % P;
+        double a[NQ];
 #pragma unroll
-        for (int j = 0; j < P; ++j) a[j] = (i < P) ? G[i * P + j] : 0.0;
+        for (int q = 0; q < NQ; ++q) a[q] = G[(i0 + RPL * q) * P + k];
         double dmax = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) dmax = fmax(dmax, readlane_d(a[j], j));
+        for (int j = 0; j < P; ++j) dmax = fmax(dmax, readlane_d(a[j / RPL], j + P * (j % RPL)));
         const double thr = tol * dmax;
         double inv_d[P];
+        double* colbuf = Linv;           // row j: column j of L, entry (i % RPL) * NQ + i / RPL
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            const double d = readlane_d(a[j], j);
+            const double d = readlane_d(a[j / RPL], j + P * (j % RPL));
             const bool dj = !(d > thr);
             const double piv = dj ? 0.0 : __builtin_sqrt(d);
             const double inv = dj ? 0.0 : 1.0 / piv;
             inv_d[j] = inv;
-            const double lij = (i > j) ? a[j] * inv : ((i == j) ? piv : 0.0);
-            a[j] = lij;
+            if (k == j) {
 #pragma unroll
-            for (int k = j + 1; k < P; ++k) {
-                const double lk = readlane_d(lij, k);
-                if (i >= k) a[k] = __builtin_fma(-lij, lk, a[k]);
+                for (int q = 0; q < NQ; ++q) {
+                    const int i = i0 + RPL * q;
+                    const double lij = (i > j) ? a[q] * inv : ((i == j) ? piv : 0.0);
+                    a[q] = lij;
+                    colbuf[j * P + i0 * NQ + q] = lij;
+                }
             }
-            if (i == 0) dead[j] = dj ? 1 : 0;
+            __builtin_amdgcn_wave_barrier();     // keep the other lanes' reads after these writes
+            double li[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) li[q] = colbuf[j * P + i0 * NQ + q];
+            const double lk = colbuf[j * P + (k % RPL) * NQ + k / RPL];
+            if (k > j) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (i0 + RPL * q >= k) a[q] = __builtin_fma(-li[q], lk, a[q]);
+            }
+            if (l == 0) dead[j] = dj ? 1 : 0;
         }
-        // Linv by forward elimination on [L | I], rows in order
-        double x[P];
+        // Linv by forward elimination on [L | I]: row m is final once the rows
+        // above it have been subtracted; it is published and subtracted below
+        double x[NQ];
 #pragma unroll
-        for (int j = 0; j < P; ++j) x[j] = (i == j) ? 1.0 : 0.0;
+        for (int q = 0; q < NQ; ++q) x[q] = (i0 + RPL * q == k) ? 1.0 : 0.0;
+        double* rowbuf = L;
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            if (i == k) {
-#pragma unroll
-                for (int j = 0; j <= k; ++j) x[j] *= inv_d[k];
+        for (int m = 0; m < P; ++m) {
+            if (i0 == m % RPL) {
+                x[m / RPL] *= inv_d[m];
+                rowbuf[m * P + k] = x[m / RPL];
             }
-            if (i > k) {
-                const double lik = a[k];
+            __builtin_amdgcn_wave_barrier();
+            double lm[NQ];
 #pragma unroll
-                for (int j = 0; j <= k; ++j) x[j] = __builtin_fma(-lik, readlane_d(x[j], k), x[j]);
-            } else {
+            for (int q = 0; q < NQ; ++q) lm[q] = colbuf[m * P + i0 * NQ + q];
+            const double xm = rowbuf[m * P + k];
 #pragma unroll
-                for (int j = 0; j <= k; ++j) (void)readlane_d(x[j], k);
-            }
+            for (int q = 0; q < NQ; ++q)
+                if (i0 + RPL * q > m) x[q] = __builtin_fma(-lm[q], xm, x[q]);
         }
-        if (i < P) {
+        __builtin_amdgcn_wave_barrier();         // the buffers are overwritten below
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                L[i * P + j] = (j <= i) ? a[j] : 0.0;
-                Linv[i * P + j] = (j <= i) ? x[j] : 0.0;
-            }
+        for (int q = 0; q < NQ; ++q) {
+            const int i = i0 + RPL * q;
+            L[i * P + k] = (k <= i) ? a[q] : 0.0;
+            Linv[i * P + k] = (k <= i) ? x[q] : 0.0;
         }
     }
     __syncthreads();
