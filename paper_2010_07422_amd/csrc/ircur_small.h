@@ -246,18 +246,20 @@ __device__ void orthonormalise(double* X, int m16, int rows_valid, int live, dou
     int maxp = passes;
     for (int pass = 0; pass < maxp; ++pass) {
         mm_small<P, true, false>(X, P, X, P, Gs, m16, scratch);
-        // orthonormality defect
-        double dev = 0.0;
-        for (int e = threadIdx.x; e < P * P; e += NT) {
-            const int i = e / P, j = e - i * P;
-            if (i < live && j < live) dev = fmax(dev, fabs(Gs[e] - (i == j ? 1.0 : 0.0)));
+        if (pass > 0) {
+            // orthonormality defect after a pass: stop once it is at rounding level
+            double dev = 0.0;
+            for (int e = threadIdx.x; e < P * P; e += NT) {
+                const int i = e / P, j = e - i * P;
+                if (i < live && j < live) dev = fmax(dev, fabs(Gs[e] - (i == j ? 1.0 : 0.0)));
+            }
+            for (int off = 32; off >= 1; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+            __syncthreads();
+            const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();
+            if (!(dmax > 1e-13)) break;
         }
-        for (int off = 32; off >= 1; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
-        __syncthreads();
-        const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        __syncthreads();
-        if (!(dmax > 1e-13) && pass > 0) break;
         chol_inv<P>(Gs, Ls, Li, dead, 1e-14);
         mm_rows<P, false, true>(X, P, Li, P, X, P, m16, P, rows_valid);
         __syncthreads();

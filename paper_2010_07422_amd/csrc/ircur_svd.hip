@@ -559,28 +559,54 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
     bool conv = false;
     double rho = 0.0;
     for (;;) {
-        // Y_blk = M_blk Q
-        for (int t = w4; t < bs16 / 16; t += 4) {
-            d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-            if (t < nt_rows) {
-                const double* ma = Mb + (size_t)t * KSA * 64 + l64;
-                for (int k0 = 0; k0 < KSA; k0 += 8) {
-                    double av[8], bv[8];
+        // Y_blk = M_blk Q.  With fewer row tiles than waves the k range is
+        // split too (ks parts per tile), so that all four waves work; the
+        // parts are added in a fixed order.
+        {
+            const int ntl = bs16 / 16;
+            const int ks = ntl >= 4 ? 1 : 4 / ntl;      // ntl * ks <= 4 partial tiles in scr
+            const int kper = (KSA + ks - 1) / ks;
+            for (int w = w4; w < ntl * ks; w += 4) {
+                const int t = w % ntl, h = w / ntl;
+                const int kb = min(KSA, h * kper), ke = min(KSA, (h + 1) * kper);
+                d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+                if (t < nt_rows) {
+                    const double* ma = Mb + (size_t)t * KSA * 64 + l64;
+                    for (int k0 = kb; k0 < ke; k0 += 8) {
+                        double av[8], bv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const bool in = k0 + u < KSA;
-                        av[u] = in ? ma[(size_t)(k0 + u) * 64] : 0.0;
-                        bv[u] = in ? Q[(4 * (k0 + u) + (l64 >> 4)) * P + (l64 & 15)] : 0.0;
-                    }
+                        for (int u = 0; u < 8; ++u) {
+                            const bool in = k0 + u < ke;
+                            av[u] = in ? ma[(size_t)(k0 + u) * 64] : 0.0;
+                            bv[u] = in ? Q[(4 * (k0 + u) + (l64 >> 4)) * P + (l64 & 15)] : 0.0;
+                        }
 #pragma unroll
-                    for (int u = 0; u < 8; u += 2) {
-                        if (k0 + u < KSA) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
-                        if (k0 + u + 1 < KSA) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                        for (int u = 0; u < 8; u += 2) {
+                            if (k0 + u < ke) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+                            if (k0 + u + 1 < ke) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                        }
                     }
                 }
+                acc += acc2;
+                if (ks == 1) {
+                    tile_store(Y, P, t * 16, 0, acc, nb);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) scr[(size_t)w * P * P + (l64 >> 4) * P * 4 + v * P + (l64 & 15)] = acc[v];
+                }
             }
-            acc += acc2;
-            tile_store(Y, P, t * 16, 0, acc, nb);
+            if (ks > 1) {
+                __syncthreads();
+                // part h of tile t sits in scr[(h * ntl + t) * P * P]: lane layout (row group, v, column)
+                for (int e = tid; e < ntl * 16 * P; e += NT) {
+                    const int t = e / (16 * P), rem = e - t * 16 * P;
+                    const int row = rem / P, col = rem - row * P;
+                    const int li = (row & 3) * P * 4 + (row >> 2) * P + col;   // v = row >> 2, group = row & 3
+                    double y = 0.0;
+                    for (int h = 0; h < ks; ++h) y += scr[(size_t)(h * ntl + t) * P * P + li];
+                    Y[(t * 16 + row) * P + col] = (t * 16 + row < nb) ? y : 0.0;
+                }
+            }
         }
         __syncthreads();
         PHASE(2);
