@@ -233,6 +233,8 @@ __device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, do
     __syncthreads();
 }
 
+// Returns the number of Cholesky passes applied (1: a single pass, no column
+// refilled, so Ls holds the Cholesky factor of the input's Gram matrix).
 // Orthonormalise the first `live` columns of X (m16 x P, LDS, row stride P)
 // in place by Cholesky QR (X <- X Linv^T with X^T X = L L^T), repeated while
 // max |X^T X - I| exceeds 1e-13 (at most `passes` passes, 4 once a column
@@ -240,10 +242,11 @@ __device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, do
 // is refilled with pseudo-random entries and the pass repeated; columns at or
 // past `live` stay zero.
 template <int P>
-__device__ void orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
-                               double* Li, int* dead, double* scratch, double* red, uint64_t salt,
-                               int passes = 4) {
+__device__ int orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
+                              double* Li, int* dead, double* scratch, double* red, uint64_t salt,
+                              int passes = 4) {
     int maxp = passes;
+    int done = 0;
     for (int pass = 0; pass < maxp; ++pass) {
         mm_small<P, true, false>(X, P, X, P, Gs, m16, scratch);
         if (pass > 0) {
@@ -261,6 +264,7 @@ __device__ void orthonormalise(double* X, int m16, int rows_valid, int live, dou
             if (!(dmax > 1e-13)) break;
         }
         chol_inv<P>(Gs, Ls, Li, dead, 1e-14);
+        ++done;
         mm_rows<P, false, true>(X, P, Li, P, X, P, m16, P, rows_valid);
         __syncthreads();
         int nd = 0;
@@ -274,6 +278,7 @@ __device__ void orthonormalise(double* X, int m16, int rows_valid, int live, dou
             __syncthreads();
         }
     }
+    return done;
 }
 
 }  // namespace

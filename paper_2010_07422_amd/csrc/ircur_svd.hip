@@ -550,7 +550,14 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
     }
     __syncthreads();
     PHASE(0);
-    if (warm == 2) orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red, a.salt + 17, 1);
+    // with a warm start from B_k[:, J], Q0 = B_k[:, J]^T and one Cholesky-QR
+    // pass Q = Q0 L0^-T, so that Gamma' = B_k[:, J] Q = Q0^T Q = L0 as long as
+    // Q is not replaced: L0 is kept for the epilogue
+    bool have_l0 = false;
+    if (warm == 2) {
+        have_l0 = orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red, a.salt + 17, 1) == 1;
+        for (int e = tid; e < P * P; e += NT) Gam2[e] = Ls[e];
+    }
     else if (warm == 0) orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red, a.salt + 17);
     __syncthreads();
     PHASE(1);
@@ -698,7 +705,8 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         TA[e] = Li[j * P + i];
     }
     __syncthreads();
-    mm_small<P, false, false>(a.Bsc, sJ16, Q, P, Gam2, sJ16, scr);   // Gamma' = B_k[:, J] Q
+    if (!(have_l0 && it == 1))
+        mm_small<P, false, false>(a.Bsc, sJ16, Q, P, Gam2, sJ16, scr);   // Gamma' = B_k[:, J] Q
     PHASE(8);
     mm_rows<P, false, false>(Wb, P, Gam, P, Y, P, bs16, P, nb);     // Delta_blk (into Y)
     __syncthreads();
