@@ -538,15 +538,19 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         const int ar = e / P;
         Ab[e] = ar < nb ? a.Abc[(size_t)(a0 + ar) * P + (e - ar * P)] : 0.0;
     }
-    for (int e = tid; e < sJ16 * P; e += NT) {
-        const int b = e / P, c = e - b * P;
-        double v = 0.0;
-        if (b < sJ && c < r) {
-            if (warm == 1) v = a.prevV[b * R + c];
-            else if (warm == 2) v = a.Bsc[(size_t)c * sJ16 + b];
-            else v = rnd_unit(a.salt, (uint64_t)e);
+    if (warm == 2) {
+        // B_k[:, J] read along J (coalesced), written transposed
+        for (int e = tid; e < sJ16 * P; e += NT) {
+            const int c = e / sJ16, b = e - c * sJ16;
+            Q[b * P + c] = (b < sJ && c < r) ? a.Bsc[(size_t)c * sJ16 + b] : 0.0;
         }
-        Q[e] = v;
+    } else {
+        for (int e = tid; e < sJ16 * P; e += NT) {
+            const int b = e / P, c = e - b * P;
+            double v = 0.0;
+            if (b < sJ && c < r) v = warm == 1 ? a.prevV[b * R + c] : rnd_unit(a.salt, (uint64_t)e);
+            Q[e] = v;
+        }
     }
     __syncthreads();
     PHASE(0);
