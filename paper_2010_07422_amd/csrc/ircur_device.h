@@ -37,6 +37,15 @@ __device__ __forceinline__ F entry_value(F d, F dot, double zeta, float zeta_f, 
     return o ? d - x : d;
 }
 
+// Pointers that come out of argument tables in memory are generic to the
+// compiler, and generic (flat) accesses also hold up the waits for LDS
+// results.  gp() gives such a pointer its global address space.
+typedef __attribute__((address_space(1))) double gdouble;
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     // Fixed butterfly over the 64 lanes: every lane ends with the same sum,
     // formed in the same order on every run.

@@ -251,6 +251,7 @@ struct UBack {
     double* P1; double* P2;               // sI x R, sJ x R workspace
     double* dz;                           // this step's zeta gradient (one value)
     int32_t* flags;                       // bit 0: CG did not converge, bit 1: rank < r
+    DevState* st;                         // the instance's run state (phase timers of profile builds)
 };
 
 // Launchers (return hipError_t of the launch).

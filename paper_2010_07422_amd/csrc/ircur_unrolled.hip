@@ -542,13 +542,62 @@ __device__ void jacobi16(double* K, double* Vm, int r) {
     __syncthreads();
 }
 
+// C (m16 x 16) = op(A) B with A in global memory (TA: A is K x m16, read
+// transposed) and B (K x 16) in LDS.  Each wave takes every fourth 16-row tile
+// and works on up to four of them at once, so that the global operands of
+// 4 x 8 k-steps are in flight together; rows of C at or past rows_valid are
+// written as zero.
+template <bool TA>
+__device__ void mm_rows_gA(const gdouble* __restrict__ A, int lda, const double* B, double* C, int m16, int K,
+                           int rows_valid) {
+    constexpr int MT = 4;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int ntile = m16 >> 4;
+    const int ii = l & 15, kk = l >> 4;
+    for (int t0 = w; t0 < ntile; t0 += 4 * MT) {
+        d4 acc[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < K; kb += 32) {
+            double av[MT][8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = kb + 4 * u;
+                bv[u] = k < K ? B[(k + kk) * 16 + ii] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int t = t0 + 4 * m;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = kb + 4 * u;
+                    const int i = t * 16 + ii;
+                    av[m][u] = (t < ntile && k < K) ? (TA ? A[(size_t)(k + kk) * lda + i] : A[(size_t)i * lda + k + kk])
+                                                    : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (kb + 4 * u < K) {
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        if (t0 + 4 * m < ntile) acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m][u], bv[u], acc[m], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            if (t0 + 4 * m < ntile) tile_store(C, 16, (t0 + 4 * m) * 16, 0, acc[m], rows_valid);
+    }
+}
+
 // Conjugate gradients, one system per column c < r:
 //     (sig2[c] I - A B) x_c = rhs_c    (op = A B: the two products of M_perp)
 // on m16 x 16 LDS blocks X (solution), Rr (rhs in, residual out), Pp, AP,
 // with Tm (mo16 x 16) for the inner product.  Returns 1 if some column did
 // not reach the tolerance.
 template <bool LEFT>
-__device__ int cg_solve(const double* Mp, int sI16, int sJ16, int sI, int sJ, const double* sig2, int r,
+__device__ int cg_solve(const gdouble* Mp, int sI16, int sJ16, int sI, int sJ, const double* sig2, int r,
                         double* X, double* Rr, double* Pp, double* AP, double* Tm, double* part, double* cols,
                         int max_it, double tol) {
     const int m16 = LEFT ? sI16 : sJ16, m = LEFT ? sI : sJ;
@@ -575,13 +624,13 @@ __device__ int cg_solve(const double* Mp, int sI16, int sJ16, int sI, int sJ, co
         if (done) break;
         // AP = sig2 P - Mp (Mp^T P)   (LEFT)   or   sig2 P - Mp^T (Mp P)
         if (LEFT) {
-            mm_rows<16, true, false>(Mp, sJ16, Pp, 16, Tm, 16, sJ16, sI16, sJ);
+            mm_rows_gA<true>(Mp, sJ16, Pp, Tm, sJ16, sI16, sJ);
             __syncthreads();
-            mm_rows<16, false, false>(Mp, sJ16, Tm, 16, AP, 16, sI16, sJ16, sI);
+            mm_rows_gA<false>(Mp, sJ16, Tm, AP, sI16, sJ16, sI);
         } else {
-            mm_rows<16, false, false>(Mp, sJ16, Pp, 16, Tm, 16, sI16, sJ16, sI);
+            mm_rows_gA<false>(Mp, sJ16, Pp, Tm, sI16, sJ16, sI);
             __syncthreads();
-            mm_rows<16, true, false>(Mp, sJ16, Tm, 16, AP, 16, sJ16, sI16, sJ);
+            mm_rows_gA<true>(Mp, sJ16, Tm, AP, sJ16, sI16, sJ);
         }
         __syncthreads();
         for (int e = threadIdx.x; e < m16 * 16; e += NT) {
@@ -612,9 +661,25 @@ __device__ int cg_solve(const double* Mp, int sI16, int sJ16, int sI, int sJ, co
     return fail;
 }
 
+#ifdef IRCUR_PHASE_PROFILE
+#define UPHASE(i)                                                              \
+    do {                                                                       \
+        if (blockIdx.x == 0 && threadIdx.x == 0) {                             \
+            const uint64_t t_ = __builtin_amdgcn_s_memrealtime();              \
+            u.st->phase[i] += t_ - t_prev;                                     \
+            t_prev = t_;                                                       \
+        }                                                                      \
+    } while (0)
+#else
+#define UPHASE(i) do { } while (0)
+#endif
+
 __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ arr, int max_it, double tol) {
     extern __shared__ double smem[];
     const UBack& u = arr[blockIdx.x];
+#ifdef IRCUR_PHASE_PROFILE
+    uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
+#endif
     const int R = u.R, r = u.r, sI = u.sI, sJ = u.sJ;
     const int sI16 = ((sI + 15) / 16) * 16, sJ16 = ((sJ + 15) / 16) * 16;
     const int m16 = sI16 > sJ16 ? sI16 : sJ16;
@@ -638,7 +703,7 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
     // singular triplets of H_r(M) = Wt Kc Q^T:  Kc = U_k Sigma V_k^T
     for (int e = tid; e < 256; e += NT) {
         const int i = e >> 4, j = e & 15;
-        K[e] = (i < R && j < R) ? u.Kc[i * R + j] : 0.0;
+        K[e] = (i < R && j < R) ? gp(u.Kc)[i * R + j] : 0.0;
     }
     __syncthreads();
     jacobi16(K, Vm, r);
@@ -657,7 +722,7 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
             sig[c] = c < r ? part[order[c]] : 0.0;
             sig2[c] = sig[c] * sig[c];
         }
-        if (!(sig[r - 1] > 2.220446049250313e-16 * (double)(sI > sJ ? sI : sJ) * sig[0])) u.flags[0] |= 2;
+        if (!(sig[r - 1] > 2.220446049250313e-16 * (double)(sI > sJ ? sI : sJ) * sig[0])) gp(u.flags)[0] |= 2;
     }
     __syncthreads();
     for (int e = tid; e < 256; e += NT) {
@@ -667,33 +732,47 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
         Vk[e] = ok ? Vm[i * 16 + order[c]] : 0.0;
     }
     __syncthreads();
+    UPHASE(9);
     // W_r = Wt U_k,  V_r = Q V_k,  Tp = Q Ly^-T
     for (int e = tid; e < sI * R; e += NT) {
         const int a = e / R, c = e - a * R;
         double s = 0.0;
-        for (int f = 0; f < R; ++f) s = __builtin_fma(u.Wt[a * R + f], Uk[f * 16 + c], s);
-        u.Wr[e] = s;
+        for (int f = 0; f < R; ++f) s = __builtin_fma(gp(u.Wt)[a * R + f], Uk[f * 16 + c], s);
+        gp(u.Wr)[e] = s;
     }
     for (int e = tid; e < sJ * R; e += NT) {
         const int b = e / R, c = e - b * R;
         double s = 0.0, t = 0.0;
         for (int f = 0; f < R; ++f) {
-            s = __builtin_fma(u.Q[b * R + f], Vk[f * 16 + c], s);
-            t = __builtin_fma(u.Q[b * R + f], u.TAd[f * R + c], t);
+            s = __builtin_fma(gp(u.Q)[b * R + f], Vk[f * 16 + c], s);
+            t = __builtin_fma(gp(u.Q)[b * R + f], gp(u.TAd)[f * R + c], t);
         }
-        u.Vr[e] = s;
-        u.Tp[e] = t;
+        gp(u.Vr)[e] = s;
+        gp(u.Tp)[e] = t;
     }
-    // Wbar = sum of row partials (sI x R) into B0, Tbar (sJ x R) into B1
+    // Wbar = sum of row partials (sI x R) into B0, Tbar (sJ x R) into B1: one
+    // thread per entry (a, c < R), the partials of 16 workgroups loaded
+    // together and added in workgroup order
     for (int e = tid; e < m16 * 16; e += NT) {
-        const int a = e >> 4, c = e & 15;
-        double s0 = 0.0, s1 = 0.0;
-        if (c < R && a < sI)
-            for (int w = 0; w < u.nwg_row; ++w) s0 += u.partI[((int64_t)w * sI + a) * R + c];
-        if (c < R && a < sJ)
-            for (int w = 0; w < u.nwg_col; ++w) s1 += u.partJ[((int64_t)w * sJ + a) * R + c];
-        B0[e] = s0;
-        B1[e] = s1;
+        B0[e] = 0.0;
+        B1[e] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < (sI + sJ) * R; e += NT) {
+        const bool row = e < sI * R;
+        const int ee = row ? e : e - sI * R;
+        const int a = ee / R, c = ee - a * R;
+        const int nw = row ? u.nwg_row : u.nwg_col, sn = row ? sI : sJ;
+        const gdouble* __restrict__ pp = gp(row ? u.partI : u.partJ);
+        double acc = 0.0;
+        for (int w0 = 0; w0 < nw; w0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = w0 + q < nw ? pp[((int64_t)(w0 + q) * sn + a) * R + c] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc += v[q];
+        }
+        (row ? B0 : B1)[a * 16 + c] = acc;
     }
     __syncthreads();
     // P1t = Wbar U_k Sigma (sI x r), P2 = Tbar U_k (sJ x r)
@@ -710,101 +789,165 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
         B3[e] = (a < sJ) ? s1 : 0.0;
     }
     __syncthreads();
-    // Urr = P1 W_r (r x r); M_perp = M - W_r Sigma V_r^T (padded, global)
-    {
-        const int c = tid >> 4, e = tid & 15;
-        double s = 0.0;
-        if (c < r && e < r)
-            for (int a = 0; a < sI; ++a) s = __builtin_fma(B2[a * 16 + c], u.Wr[a * R + e], s);
-        Urr[tid] = s;
-    }
-    for (int e = tid; e < sI16 * sJ16; e += NT) {
-        const int a = e / sJ16, b = e - a * sJ16;
-        double v = 0.0;
-        if (a < sI && b < sJ) {
-            v = u.M[(int64_t)a * sJ + b];
-            for (int c = 0; c < r; ++c) v = __builtin_fma(-u.Wr[a * R + c] * sig[c], u.Vr[b * R + c], v);
+    UPHASE(10);
+    // W_r and V_r into LDS (B0, B1 are free until the solves), 8 entries per
+    // thread in flight
+    for (int e0 = tid; e0 < m16 * 16; e0 += NT * 8) {
+        double w[8], v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = e0 + q * NT;
+            const int a = e >> 4, c = e & 15;
+            w[q] = (e < m16 * 16 && a < sI && c < r) ? gp(u.Wr)[a * R + c] : 0.0;
+            v[q] = (e < m16 * 16 && a < sJ && c < r) ? gp(u.Vr)[a * R + c] : 0.0;
         }
-        u.Mperp[e] = v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = e0 + q * NT;
+            if (e < m16 * 16) {
+                B0[e] = w[q];
+                B1[(e & 15) * m16 + (e >> 4)] = v[q];   // V_r^T: lanes along b read consecutive words
+            }
+        }
     }
-    // right-hand sides projected on the complements: P1t - W_r (W_r^T P1t), P2 - V_r (V_r^T P2)
+    __syncthreads();
+    // Urr = P1 W_r (r x r); W_r^T P1t and V_r^T P2 (r x r)
     {
         const int c = tid >> 4, e = tid & 15;
-        double s0 = 0.0, s1 = 0.0;
+        double s = 0.0, s0 = 0.0, s1 = 0.0;
         if (c < r && e < r) {
-            for (int a = 0; a < sI; ++a) s0 = __builtin_fma(u.Wr[a * R + c], B2[a * 16 + e], s0);
-            for (int b = 0; b < sJ; ++b) s1 = __builtin_fma(u.Vr[b * R + c], B3[b * 16 + e], s1);
+#pragma unroll 8
+            for (int a = 0; a < sI; ++a) {
+                s = __builtin_fma(B2[a * 16 + c], B0[a * 16 + e], s);
+                s0 = __builtin_fma(B0[a * 16 + c], B2[a * 16 + e], s0);
+            }
+#pragma unroll 8
+            for (int b = 0; b < sJ; ++b) s1 = __builtin_fma(B1[c * m16 + b], B3[b * 16 + e], s1);
         }
+        Urr[tid] = s;
         K[tid] = s0;    // W_r^T P1t  (r x r)
         Vm[tid] = s1;   // V_r^T P2
     }
+    // M_perp = M - W_r Sigma V_r^T (padded, global): each wave takes rows a
+    // (4 at a time, 12 entries of M per lane in flight), lanes run along b.  A
+    // lane keeps the V_r rows of its three columns in registers and takes
+    // -W_r[a, :] Sigma once per row; all 16 columns are summed (W_r, V_r and
+    // sigma are zero at and past r, so the extra terms add exact zeros).
+    {
+        const int w4 = tid >> 6, l64 = tid & 63;
+        double vb[3][16];
+#pragma unroll
+        for (int jb = 0; jb < 3; ++jb) {
+            const int bc = l64 + 64 * jb;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) vb[jb][c] = bc < sJ16 ? B1[c * m16 + bc] : 0.0;
+        }
+        for (int a0 = w4; a0 < sI16; a0 += 16) {
+            double mv[4][3];
+#pragma unroll
+            for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+                for (int jb = 0; jb < 3; ++jb) {
+                    const int ar = a0 + 4 * ia, bc = l64 + 64 * jb;
+                    mv[ia][jb] = (ar < sI && bc < sJ) ? gp(u.M)[(int64_t)ar * sJ + bc] : 0.0;
+                }
+#pragma unroll
+            for (int ia = 0; ia < 4; ++ia) {
+                const int ar = a0 + 4 * ia;
+                if (ar < sI16) {
+                    double wr[16];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) wr[c] = -B0[ar * 16 + c] * sig[c];
+#pragma unroll
+                    for (int jb = 0; jb < 3; ++jb) {
+                        const int bc = l64 + 64 * jb;
+                        if (bc < sJ16) {
+                            double v = 0.0;
+                            if (ar < sI && bc < sJ) {
+                                v = mv[ia][jb];
+#pragma unroll
+                                for (int c = 0; c < 16; ++c) v = __builtin_fma(wr[c], vb[jb][c], v);
+                            }
+                            gp(u.Mperp)[(int64_t)ar * sJ16 + bc] = v;
+                        }
+                    }
+                }
+            }
+        }
+    }
     __syncthreads();
-    // keep P2 (projected) in global P2; W side first
+    // right-hand sides projected on the complements: P1t - W_r (W_r^T P1t) into
+    // B4 (W side), P2 - V_r (V_r^T P2) kept in global P2
     for (int e = tid; e < m16 * 16; e += NT) {
         const int a = e >> 4, c = e & 15;
         double w = 0.0, v = 0.0;
         if (c < r) {
             w = B2[e];
             v = B3[e];
-            for (int f = 0; f < r; ++f) {
-                if (a < sI) w = __builtin_fma(-u.Wr[a * R + f], K[f * 16 + c], w);
-                if (a < sJ) v = __builtin_fma(-u.Vr[a * R + f], Vm[f * 16 + c], v);
+#pragma unroll
+            for (int f = 0; f < 16; ++f) {      // K, Vm are zero at and past r
+                if (a < sI) w = __builtin_fma(-B0[a * 16 + f], K[f * 16 + c], w);
+                if (a < sJ) v = __builtin_fma(-B1[f * m16 + a], Vm[f * 16 + c], v);
             }
         }
-        B1[e] = (a < sI) ? w : 0.0;            // W-side rhs
-        if (a < sJ && c < R) u.P2[a * R + c] = (c < r) ? v : 0.0;
+        B4[e] = (a < sI) ? w : 0.0;
+        if (a < sJ && c < R) gp(u.P2)[a * R + c] = (c < r) ? v : 0.0;
     }
     __syncthreads();
+    UPHASE(12);
     int fail = 0;
-    // W side:  (sig_c^2 I - M_perp M_perp^T) x_c = rhs_c
-    fail |= cg_solve<true>(u.Mperp, sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+    // W side:  (sig_c^2 I - M_perp M_perp^T) x_c = rhs_c  (rhs in B4; B1 serves as scratch)
+    fail |= cg_solve<true>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B4, B2, B3, B1, part, cols, max_it, tol);
+    UPHASE(13);
     // Qm = x / sigma (into B0), then M_perp^T Qm (sJ x 16) into B4
     for (int e = tid; e < m16 * 16; e += NT) {
         const int c = e & 15;
         B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;
     }
     __syncthreads();
-    mm_rows<16, true, false>(u.Mperp, sJ16, B0, 16, B4, 16, sJ16, sI16, sJ);
+    mm_rows_gA<true>(gp(u.Mperp), sJ16, B0, B4, sJ16, sI16, sJ);
     __syncthreads();
     // stash Qm in P1 and M_perp^T Qm in X2 (global)
     for (int e = tid; e < sI * R; e += NT) {
         const int a = e / R, c = e - a * R;
-        u.P1[e] = B0[a * 16 + c];
+        gp(u.P1)[e] = B0[a * 16 + c];
     }
     for (int e = tid; e < sJ * R; e += NT) {
         const int b = e / R, c = e - b * R;
-        u.X2[e] = B4[b * 16 + c];
+        gp(u.X2)[e] = B4[b * 16 + c];
     }
     __syncthreads();
     // V side:  (sig_c^2 I - M_perp^T M_perp) y_c = rhs_c
     for (int e = tid; e < m16 * 16; e += NT) {
         const int a = e >> 4, c = e & 15;
-        B1[e] = (a < sJ && c < R) ? u.P2[a * R + c] : 0.0;
+        B1[e] = (a < sJ && c < R) ? gp(u.P2)[a * R + c] : 0.0;
     }
     __syncthreads();
-    fail |= cg_solve<false>(u.Mperp, sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+    UPHASE(14);
+    fail |= cg_solve<false>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+    UPHASE(15);
     for (int e = tid; e < m16 * 16; e += NT) {
         const int c = e & 15;
         B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;   // Um
     }
     __syncthreads();
-    mm_rows<16, false, false>(u.Mperp, sJ16, B0, 16, B4, 16, sI16, sJ16, sI);   // M_perp Um (sI x 16)
+    mm_rows_gA<false>(gp(u.Mperp), sJ16, B0, B4, sI16, sJ16, sI);   // M_perp Um (sI x 16)
     __syncthreads();
     // X1 = Qm Sigma + M_perp Um - W_r Sigma^-1 Urr Sigma^-1,  X2 = M_perp^T Qm + Um Sigma
     for (int e = tid; e < sI * R; e += NT) {
         const int a = e / R, c = e - a * R;
         double v = 0.0;
         if (c < r) {
-            v = __builtin_fma(u.P1[e], sig[c], B4[a * 16 + c]);
-            for (int f = 0; f < r; ++f) v = __builtin_fma(-u.Wr[a * R + f], Urr[f * 16 + c] / (sig[f] * sig[c]), v);
+            v = __builtin_fma(gp(u.P1)[e], sig[c], B4[a * 16 + c]);
+            for (int f = 0; f < r; ++f) v = __builtin_fma(-gp(u.Wr)[a * R + f], Urr[f * 16 + c] / (sig[f] * sig[c]), v);
         }
-        u.X1[e] = v;
+        gp(u.X1)[e] = v;
     }
     for (int e = tid; e < sJ * R; e += NT) {
         const int b = e / R, c = e - b * R;
-        u.X2[e] = c < r ? __builtin_fma(B0[b * 16 + c], sig[c], u.X2[e]) : 0.0;
+        gp(u.X2)[e] = c < r ? __builtin_fma(B0[b * 16 + c], sig[c], gp(u.X2)[e]) : 0.0;
     }
-    if (tid == 0 && fail) u.flags[0] |= 1;
+    if (tid == 0 && fail) gp(u.flags)[0] |= 1;
 }
 
 template <typename F>

@@ -9,6 +9,7 @@
 // every step) stays in HBM; the gathered rows and columns are recomputed in
 // the reverse sweep.
 #include "ircur_internal.h"
+#include <cstdio>
 #include "../../include/ircur.h"
 
 #include <algorithm>
@@ -418,6 +419,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             ub.P1 = h.P1; ub.P2 = h.P2;
             ub.dz = u->dz_inst + e;
             ub.flags = u->flags + b;
+            ub.st = u->st + b;
         }
     }
     for (int b = 0; b < nb; ++b) {
@@ -529,6 +531,16 @@ int ircur_unrolled_status(ircur_unrolled* u, int32_t* flags_host) {
 void ircur_unrolled_destroy(ircur_unrolled* u) {
     if (!u) return;
     (void)hipStreamSynchronize(u->stream);
+#ifdef IRCUR_PHASE_PROFILE
+    {
+        DevState h{};
+        if (hipMemcpy(&h, u->st, sizeof(DevState), hipMemcpyDeviceToHost) == hipSuccess) {
+            std::fprintf(stderr, "ubsmall phases of instance 0 (total us):");
+            for (int i = 9; i < 16; ++i) std::fprintf(stderr, " [%d] %.1f", i, (double)h.phase[i] * 0.01);
+            std::fprintf(stderr, "\n");
+        }
+    }
+#endif
     ufree(u);
     delete u;
 }
