@@ -4,6 +4,7 @@
 #pragma once
 
 #include "ircur_internal.h"
+#include "ircur_gptr.h"
 
 #include <algorithm>
 
@@ -35,15 +36,6 @@ __device__ __forceinline__ F entry_value(F d, F dot, double zeta, float zeta_f, 
     const bool o = above(x < F(0) ? -x : x, zeta, zeta_f);
     *is_out = o;
     return o ? d - x : d;
-}
-
-// Pointers that come out of argument tables in memory are generic to the
-// compiler, and generic (flat) accesses also hold up the waits for LDS
-// results.  gp() gives such a pointer its global address space.
-typedef __attribute__((address_space(1))) double gdouble;
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
-    return (__attribute__((address_space(1))) T*)p;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

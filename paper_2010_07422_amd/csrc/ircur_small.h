@@ -5,6 +5,7 @@
 #pragma once
 
 #include "ircur_internal.h"
+#include "ircur_gptr.h"
 
 #include <stdint.h>
 
@@ -15,13 +16,15 @@ namespace {
 constexpr int NT = 256;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Factor and per-row arrays in global memory, double or float (F32 and BF16
+// modes); typed global so that no generic access is generated.
 __device__ __forceinline__ double fget(const void* p, int64_t i, int dt) {
-    if (dt == 0) return ((const double*)p)[i];
-    return (double)((const float*)p)[i];   // float factors (F32 and BF16 modes)
+    if (dt == 0) return ((const __attribute__((address_space(1))) double*)p)[i];
+    return (double)((const __attribute__((address_space(1))) float*)p)[i];
 }
 __device__ __forceinline__ void fput(void* p, int64_t i, double v, int dt) {
-    if (dt == 0) ((double*)p)[i] = v;
-    else ((float*)p)[i] = (float)v;
+    if (dt == 0) ((__attribute__((address_space(1))) double*)p)[i] = v;
+    else ((__attribute__((address_space(1))) float*)p)[i] = (float)v;
 }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {

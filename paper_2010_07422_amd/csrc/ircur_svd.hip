@@ -60,7 +60,7 @@ __device__ void grid_barrier(uint32_t* ctr, uint32_t target, int32_t* fail) {
 
 // Sum of G partials (stride apart) in a fixed order, loads issued together.
 template <int G>
-__device__ __forceinline__ void reduce_parts(const double* __restrict__ src, size_t stride, int total,
+__device__ __forceinline__ void reduce_parts(const gdouble* __restrict__ src, size_t stride, int total,
                                              double* out) {
     constexpr int E = G <= 8 ? 7 : (G <= 16 ? 3 : 1);   // elements per thread per batch (<= 63 loads)
     for (int e0 = threadIdx.x; e0 < total; e0 += NT * E) {
@@ -317,8 +317,8 @@ __device__ __forceinline__ void svd_body(const SvdArgs& a, const int wg) {
         ++nbar;
         grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
         PHASE(4);
-        reduce_parts<G>(a.Zp, (size_t)sJ * P, sJ * P, Z);
-        reduce_parts<G>(a.Gp, (size_t)2 * P * P, 2 * P * P, Gy);   // Gy then H (adjacent in LDS)
+        reduce_parts<G>(gp(a.Zp), (size_t)sJ * P, sJ * P, Z);
+        reduce_parts<G>(gp(a.Gp), (size_t)2 * P * P, 2 * P * P, Gy);   // Gy then H (adjacent in LDS)
         for (int e = tid; e < (sJ16 - sJ) * P; e += NT) Z[sJ * P + e] = 0.0;
         __syncthreads();
         PHASE(5);
@@ -516,7 +516,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         const int have = nt_rows * KSA * 64;
         // 16-byte loads, up to 20 per thread in flight (one round trip for
         // blocks up to 80 KiB)
-        const dbl2* __restrict__ src2 = (const dbl2*)src;
+        const __attribute__((address_space(1))) dbl2* __restrict__ src2 = (const __attribute__((address_space(1))) dbl2*)src;
         dbl2* dst2 = (dbl2*)Mb;
         const int have2 = have / 2, tot2 = bs16 * sJ16 / 2;
         constexpr int V = 20;
@@ -536,19 +536,19 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
     }
     for (int e = tid; e < bs16 * P; e += NT) {
         const int ar = e / P;
-        Ab[e] = ar < nb ? a.Abc[(size_t)(a0 + ar) * P + (e - ar * P)] : 0.0;
+        Ab[e] = ar < nb ? gp(a.Abc)[(size_t)(a0 + ar) * P + (e - ar * P)] : 0.0;
     }
     if (warm == 2) {
         // B_k[:, J] read along J (coalesced), written transposed
         for (int e = tid; e < sJ16 * P; e += NT) {
             const int c = e / sJ16, b = e - c * sJ16;
-            Q[b * P + c] = (b < sJ && c < r) ? a.Bsc[(size_t)c * sJ16 + b] : 0.0;
+            Q[b * P + c] = (b < sJ && c < r) ? gp(a.Bsc)[(size_t)c * sJ16 + b] : 0.0;
         }
     } else {
         for (int e = tid; e < sJ16 * P; e += NT) {
             const int b = e / P, c = e - b * P;
             double v = 0.0;
-            if (b < sJ && c < r) v = warm == 1 ? a.prevV[b * R + c] : rnd_unit(a.salt, (uint64_t)e);
+            if (b < sJ && c < r) v = warm == 1 ? gp(a.prevV)[b * R + c] : rnd_unit(a.salt, (uint64_t)e);
             Q[e] = v;
         }
     }
@@ -623,7 +623,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         PHASE(2);
         // Z_g = M_blk^T Y_blk (sJ16 x P), column tile tj of M per work item
         {
-            double* Zp = Zp_all + (size_t)wg * sJ16 * P;
+            gdouble* Zp = gp(Zp_all) + (size_t)wg * sJ16 * P;
             const int nks = nt_rows * 4;
             for (int tj = w4; tj < ntj; tj += 4) {
                 d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -649,7 +649,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         mm_small<P, true, false>(Y, P, Y, P, Gy, bs16, scr);
         mm_small<P, true, false>(Y, P, Ab, P, H, bs16, scr);
         {
-            double* Gp = a.Gp + (size_t)wg * 2 * P * P;
+            gdouble* Gp = gp(a.Gp) + (size_t)wg * 2 * P * P;
             for (int e = tid; e < P * P; e += NT) {
                 Gp[e] = Gy[e];
                 Gp[P * P + e] = H[e];
@@ -660,8 +660,8 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
         PHASE(4);
         // reduce-scatter: full Gy and H, this workgroup's slice of Z
-        reduce_parts<G>(a.Gp, (size_t)2 * P * P, 2 * P * P, Gy);
-        reduce_parts<G>(Zp_all + (size_t)z0 * P, (size_t)sJ16 * P, zn * P, Zs);
+        reduce_parts<G>(gp(a.Gp), (size_t)2 * P * P, 2 * P * P, Gy);
+        reduce_parts<G>(gp(Zp_all) + (size_t)z0 * P, (size_t)sJ16 * P, zn * P, Zs);
         __syncthreads();
         // residual of the slice: ||Z - Q Gy||^2 over rows z0 .. z1
         double part = 0.0;
@@ -673,9 +673,9 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
             const double dz = Zs[e] - q;
             part = __builtin_fma(dz, dz, part);
         }
-        for (int e = tid; e < zn * P; e += NT) a.Zr[(size_t)z0 * P + e] = Zs[e];
+        for (int e = tid; e < zn * P; e += NT) gp(a.Zr)[(size_t)z0 * P + e] = Zs[e];
         const double num_s = block_sum(part, red);
-        if (tid == 0) a.rp[wg] = num_s;
+        if (tid == 0) gp(a.rp)[wg] = num_s;
         PHASE(5);
         ++nbar;
         grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
@@ -683,14 +683,14 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         for (int e = tid; e < P * P; e += NT) gn = __builtin_fma(Gy[e], Gy[e], gn);
         const double den = block_sum(gn, red);
         double num = 0.0;
-        for (int g = 0; g < G; ++g) num += a.rp[g];
+        for (int g = 0; g < G; ++g) num += gp(a.rp)[g];
         rho = den > 0.0 ? __builtin_sqrt(num / den) : 0.0;
         ++it;
         conv = !(rho > a.tol);
         PHASE(6);
         if (conv || it >= a.max_it) break;
         // all-gather: Q <- orth(Z)
-        batched(sJ16 * P, [&](int e) { return e < sJ * P ? a.Zr[e] : 0.0; }, [&](int e, double v) { Q[e] = v; });
+        batched(sJ16 * P, [&](int e) { return e < sJ * P ? gp(a.Zr)[e] : 0.0; }, [&](int e, double v) { Q[e] = v; });
         __syncthreads();
         orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red,
                           a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
@@ -720,7 +720,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         fput(a.rowI, base + c, Ab[ar * P + c], fd);
         fput(a.rowI, base + R + c, Wb[ar * P + c], fd);
         fput(a.rowI, base + 2 * R + c, Ab[ar * P + c] - Y[ar * P + c], fd);
-        a.W[(int64_t)(a0 + ar) * R + c] = Wb[ar * P + c];
+        gp(a.W)[(int64_t)(a0 + ar) * R + c] = Wb[ar * P + c];
     }
     const int nbj = (sJ - wg + G - 1) / G;
     for (int e = tid; e < nbj * R; e += NT) {
@@ -728,12 +728,12 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         double s = 0.0;
         for (int i = 0; i < P; ++i) s = __builtin_fma(Gam2[c * P + i], Q[b * P + i], s);
         const int64_t base = (int64_t)b * a.qs;
-        const double bcj = a.Bsc[(size_t)c * sJ16 + b];
+        const double bcj = gp(a.Bsc)[(size_t)c * sJ16 + b];
         fput(a.rowJ, base + c, bcj, fd);
         fput(a.rowJ, base + R + c, Q[b * P + c], fd);
         fput(a.rowJ, base + 2 * R + c, bcj - s, fd);
-        a.V[(int64_t)b * R + c] = Q[b * P + c];
-        if (a.prevV_out) a.prevV_out[(int64_t)b * R + c] = Q[b * P + c];
+        gp(a.V)[(int64_t)b * R + c] = Q[b * P + c];
+        if (a.prevV_out) gp(a.prevV_out)[(int64_t)b * R + c] = Q[b * P + c];
     }
     if (wg == 0) {
         for (int e = tid; e < R * R; e += NT) {
@@ -741,8 +741,8 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
             fput(a.GmI, e, Gam[c * P + d], fd);
             fput(a.GmJ, e, Gam2[d * P + c], fd);
             fput(a.scaleJ, e, TA[c * P + d], fd);
-            if (a.TAd) a.TAd[e] = TA[c * P + d];
-            a.sigma[e] = Ls[d * P + c];
+            if (a.TAd) gp(a.TAd)[e] = TA[c * P + d];
+            gp(a.sigma)[e] = Ls[d * P + c];
         }
         if (tid == 0) {
             int kept = 0;
