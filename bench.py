@@ -132,21 +132,25 @@ def run_unrolled(batch, zeta, r, K, tau, steps, warmup):
                      torch.tensor(p.W, dtype=torch.float32, device="cuda"),
                      torch.tensor(p.V, dtype=torch.float32, device="cuda"), it.s, it.s, 1000 + b))
     ub = IRCURUnrolled(inst, r, K, tau_rel=tau)
-    z = torch.tensor(zeta, dtype=torch.float32, device="cuda")
-    for _ in range(warmup):
-        ub.forward(z)
+    # the thresholds move by 0.1% from one step to the next, as under a
+    # training loop (every forward solves its own SVDs to tolerance; later
+    # forwards start them from the previous forward's subspaces)
+    zs = [torch.tensor(zeta * (1.0 + 1e-3 * (-1) ** t), dtype=torch.float32, device="cuda")
+          for t in range(max(steps, warmup) + 1)]
+    for t in range(warmup):
+        ub.forward(zs[t])
         ub.backward()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        loss = ub.forward(z)
+    for t in range(steps):
+        loss = ub.forward(zs[t + 1])
         dz = ub.backward()
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(steps):
-        ub.forward(z)
+    for q in range(steps):
+        ub.forward(zs[q])
     torch.cuda.synchronize()
     tf = time.perf_counter() - t1
     flags = ub.status()

@@ -90,6 +90,7 @@ struct ircur_unrolled {
     void* common = nullptr;      // argument tables, offsets, small shared arrays
     CoreArgs* d_core = nullptr;
     SvdArgs* d_svd = nullptr;
+    SvdArgs* d_svd_warm = nullptr;     // the same, warm-started from the previous forward's subspaces
     PassArgs* d_pass = nullptr;
     ULoss* d_loss = nullptr;
     UBack* d_back = nullptr;
@@ -335,6 +336,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             cv.base = (char*)u->common;
             u->d_core = cv.take<CoreArgs>(core.size());
             u->d_svd = cv.take<SvdArgs>(svd.size());
+            u->d_svd_warm = cv.take<SvdArgs>(svd.size());
             u->d_pass = cv.take<PassArgs>(pas.size());
             u->d_loss = cv.take<ULoss>(los.size());
             u->d_back = cv.take<UBack>(back.size());
@@ -433,6 +435,18 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
     }
     UHIP(hipMemcpyAsync(u->d_core, core.data(), core.size() * sizeof(CoreArgs), hipMemcpyHostToDevice, u->stream));
     UHIP(hipMemcpyAsync(u->d_svd, svd.data(), svd.size() * sizeof(SvdArgs), hipMemcpyHostToDevice, u->stream));
+    // later forward passes start each step's subspace iteration from the
+    // subspace that the previous forward found for that step (its V_k, kept
+    // in the tape and overwritten only by this step's own SVD, after every
+    // workgroup has read it)
+    std::vector<SvdArgs> svd_warm(svd);
+    for (size_t e = 0; e < svd_warm.size(); ++e) {
+        svd_warm[e].warm = 1 | (svd[e].warm & ~0xff);
+        svd_warm[e].prevV = svd[e].V;
+        svd_warm[e].prevV_out = nullptr;
+    }
+    UHIP(hipMemcpyAsync(u->d_svd_warm, svd_warm.data(), svd_warm.size() * sizeof(SvdArgs), hipMemcpyHostToDevice,
+                        u->stream));
     UHIP(hipMemcpyAsync(u->d_pass, pas.data(), pas.size() * sizeof(PassArgs), hipMemcpyHostToDevice, u->stream));
     UHIP(hipMemcpyAsync(u->d_loss, los.data(), los.size() * sizeof(ULoss), hipMemcpyHostToDevice, u->stream));
     UHIP(hipMemcpyAsync(u->d_back, back.data(), back.size() * sizeof(UBack), hipMemcpyHostToDevice, u->stream));
@@ -457,7 +471,8 @@ int ircur_unrolled_forward(ircur_unrolled* u, const double* zeta_dev, double* lo
         const size_t e = (size_t)k * nb;
         UCHK(u, launch_ucore(u->d_core + e, u->off_core, nb, u->tot_core, u->zeta + k, u->tau_rel, u->dtype, R,
                              u->stream));
-        UCHK(u, launch_svdl_batch(u->d_svd + e, nb, u->G, u->svd_lds, u->stream));
+        UCHK(u, launch_svdl_batch((u->forward_done ? u->d_svd_warm : u->d_svd) + e, nb, u->G, u->svd_lds,
+                                  u->stream));
         UCHK(u, launch_upass(u->d_pass + e, u->off_pass, nb, u->tot_pass, u->zeta + k, u->tau_rel,
                              u->dtype, R, u->stream));
     }
