@@ -81,8 +81,9 @@ typedef struct {
     int32_t max_iter;    /* iteration cap, >= 1                                     */
     uint64_t seed;       /* index-sampler seed (SplitMix64 stream, see below)       */
     double  svd_tol;     /* relative residual tolerance of the top-r SVD; 0: default
-                            (1e-13 for F64, 1e-9 for F32, 1e-7 for BF16: four or
-                            more orders below the rounding of the stored D)        */
+                            (1e-13 for F64, 1e-9 for F32; for BF16
+                            max(1e-7, 1e-2 e_k), e_k the stopping residual of the
+                            iteration before, e_0 = 1)                              */
     int32_t svd_max_it;  /* subspace-iteration cap of the top-r SVD; 0: default 64   */
     int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default       */
 } ircur_params;

@@ -355,6 +355,10 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     sa.max_it = p.svd_max_it > 0 ? p.svd_max_it : 64;
     // default: well below the rounding of the stored D (bf16 keeps 8 bits)
     sa.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : (p.dtype == IRCUR_F32 ? 1e-9 : 1e-7));
+    // BF16 storage, default tolerance: the subspace follows the run's stopping
+    // residual, max(1e-7, 1e-2 e_k) (an SVD a hundred times finer than the
+    // iterate it updates; the last iterations get 1e-7)
+    sa.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
     bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
                  std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
     sa.warm = k == 0 ? 0 : (sameJ ? 1 : 2);

@@ -125,6 +125,7 @@ struct SvdArgs {
     int32_t bs;            // rows of M per workgroup (multiple of 16)
     int32_t max_it;
     double tol;
+    double tol_e;          // > 0: the tolerance is max(tol, tol_e * e_k) (e_0 = 1)
     int32_t warm;          // 0 random, 1 previous right basis, 2 B_k[:, J]^T
     uint64_t salt;         // random fill salt
     const double* prevV;   // sJ x R (warm == 1)

@@ -566,6 +566,9 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
     __syncthreads();
     PHASE(1);
 
+    // tolerance of this iteration: with tol_e > 0 it follows the stopping
+    // residual e_k of the run (e_0 = 1), never below tol
+    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
     int it = 0;
     bool conv = false;
     double rho = 0.0;
@@ -686,7 +689,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         for (int g = 0; g < G; ++g) num += gp(a.rp)[g];
         rho = den > 0.0 ? __builtin_sqrt(num / den) : 0.0;
         ++it;
-        conv = !(rho > a.tol);
+        conv = !(rho > tol_k);
         PHASE(6);
         if (conv || it >= a.max_it) break;
         // all-gather: Q <- orth(Z)
