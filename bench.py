@@ -10,7 +10,9 @@ accumulation, FP64 SVD): alpha = 0.3, outliers uniform in +-10 mean|L|,
 Printed: one JSON line with iterations/s (value), the roofline of the pass
 kernel (HIP events on the library's stream), the oracle's CPU rate on a
 bounded sample of the same workload, and extra figures (time to e <= 1e-5,
-the same problem in FP64, per-kernel times).
+the same problem in FP64, per-kernel times, and the 76800 x 1200 video-shaped
+FP32 instance with the bandwidth of its pass and of the full foreground
+extraction).
 """
 from __future__ import annotations
 
@@ -109,6 +111,58 @@ def run_gpu(D, p, r, s, steps, warmup, label, pass_reps=1000):
     At, B = ctx.factors()
     ctx.close()
     return out, At.double().cpu().numpy().T, B.double().cpu().numpy()
+
+
+def run_video(steps=200, warmup=20, pass_reps=200, sparse_reps=10):
+    """The 76800 x 1200 video-shaped FP32 instance (r = 2, |I| = 800, |J| = 200):
+    iterations/s, time to e <= 1e-5, the pass kernel's bandwidth (its column
+    side streams 200 rows of 76800 from D^T: 66 MB per launch), and the full
+    foreground extraction T_zeta(D - L_k) over all of D (one read of D and one
+    write of S, 737 MB)."""
+    import torch
+    from paper_2010_07422_amd import synth
+    from paper_2010_07422_amd.ircur import IRCUR
+    cfg = synth.CONFIGS["video_76800x1200_r2_f32"]
+    v = synth.video(cfg["h"], cfg["w"], cfg["frames"], seed=cfg["data_seed"])
+    Lmax = float(np.abs(v.F @ v.G.T).max())
+    r, sI, sJ = cfg["r"], cfg["sI"], cfg["sJ"]
+    n1, n2 = v.D.shape
+    D = torch.tensor(v.D, dtype=torch.float32, device="cuda")
+    out = {"workload": "video-shaped 76800 x 1200 (320 x 240 px, 1200 frames), rank-2 background + "
+                       "4 moving blobs, r=2, |I|=800, |J|=200, FP32, IRCUR-R"}
+    ctx = IRCUR(D, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=-1.0, max_iter=warmup + steps + 8,
+                seed=cfg["index_seed"], resample=True)
+    ctx.enqueue(warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.enqueue(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["iters_per_s"] = steps / t
+    pus = ctx.time_pass(pass_reps)
+    nbytes = pass_bytes(n1, n2, sI, sJ, r, 4, 4)
+    out["pass"] = {"avg_launch_us": pus, "bytes_per_launch": nbytes,
+                   "achieved_GBs": nbytes / (pus * 1e3), "frac": nbytes / (pus * 1e3) / HBM_PEAK_GBS}
+    S = torch.empty_like(D)
+    S, nnz = ctx.sparse_full(out=S)
+    sus = ctx.time_sparse(S, reps=sparse_reps)
+    sbytes = 2 * 4 * n1 * n2 + 4 * r * (n1 + n2)
+    out["sparse_full"] = {"avg_launch_us": sus, "bytes_per_launch": sbytes, "nnz": nnz,
+                          "achieved_GBs": sbytes / (sus * 1e3), "frac": sbytes / (sus * 1e3) / HBM_PEAK_GBS}
+    ctx.close()
+    ctx = IRCUR(D, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=1e-5, max_iter=100, seed=cfg["index_seed"],
+                resample=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, e, rc = ctx.solve()
+    out["time_to_1e-5_ms"] = 1e3 * (time.perf_counter() - t0)
+    out["iters_to_1e-5"] = it
+    ctx.close()
+    del D, S
+    torch.cuda.empty_cache()
+    return out
 
 
 def unrolled_items(nb=32, r=5, K=10, seed=7):
@@ -220,6 +274,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-unrolled", action="store_true")
+    ap.add_argument("--no-video", action="store_true")
     ap.add_argument("--unrolled-steps", type=int, default=20)
     ap.add_argument("--scaling", action="store_true",
                     help="also run the size sweep n = 1000..30000 (IRCUR-R and -F, BF16) and k concurrent instances")
@@ -263,6 +318,8 @@ def main():
         extra["f64"]["pass_traffic_bytes"] = measured_traffic("f64")
         extra["bf16_vs_f64_rel_L"] = O.factored_rel_diff(A_bf, B_bf, A64, B64)
     extra["bf16_vs_truth_rel_L"] = O.factored_rel_diff(A_bf, B_bf, p.W, p.V.T)
+    if not args.no_video:
+        extra["video"] = run_video()
     nbytes = pass_bytes(n, n, s, s, r, 2, 4)
     pass_us = res["pass_us"]
     achieved = nbytes / (pass_us * 1e3)     # GB/s

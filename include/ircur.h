@@ -234,6 +234,19 @@ int ircur_get_timing(ircur_ctx* ctx, double* ms4, int64_t* count);
  */
 int ircur_time_pass(ircur_ctx* ctx, int32_t reps, double* us_out);
 
+/*
+ * Duration of the full sparse-part extraction of ircur_sparse_full (the
+ * threshold of eq. (4) over all of D - A_k B_k, section 4.2's foreground)
+ * measured with HIP events on the context's stream: the extraction into S_dev
+ * (caller-owned device memory, n1 x n2 in D's storage type, leading
+ * dimension ldS >= n2) is launched `reps` times back to back, without the
+ * nonzero count, and the mean per launch in microseconds goes to *us_out.
+ * zeta < 0 picks gamma^k zeta_0 as ircur_sparse_full does.  ERR_ARG for a
+ * NULL pointer, ldS < n2, a NaN zeta or reps < 1.  Synchronises.
+ */
+int ircur_time_sparse(ircur_ctx* ctx, double zeta, void* S_dev, int64_t ldS, int32_t reps,
+                      double* us_out);
+
 /* Diagnostics of the last iteration: svd iterations, svd residual, the
  * estimated gap sigma_{r+1}/sigma_r, kept rank.  Synchronises. */
 int ircur_get_info(ircur_ctx* ctx, int32_t* svd_iters, double* svd_resid,

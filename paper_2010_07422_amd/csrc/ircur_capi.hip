@@ -825,10 +825,7 @@ int ircur_to_svd(ircur_ctx* c, double* W_dev, double* sigma_dev, double* V_dev) 
     return IRCUR_OK;
 }
 
-int ircur_sparse_full(ircur_ctx* c, double zeta, void* S_dev, int64_t ldS, int64_t* nnz_out) {
-    if (!c || !S_dev || ldS < c->p.n2 || std::isnan(zeta)) return IRCUR_ERR_ARG;
-    int rc = read_state(c);
-    if (rc) return rc;
+static SparseArgs sparse_args(const ircur_ctx* c, double zeta, void* S_dev, int64_t ldS) {
     const ircur_params& p = c->p;
     const int cur = c->k & 1;
     SparseArgs a{};
@@ -837,6 +834,15 @@ int ircur_sparse_full(ircur_ctx* c, double zeta, void* S_dev, int64_t ldS, int64
     a.zeta = zeta < 0.0 ? zeta_at(p, c->k) : zeta;
     a.zeta_f = round_down_float(a.zeta);
     a.S = S_dev; a.ldS = ldS;
+    return a;
+}
+
+int ircur_sparse_full(ircur_ctx* c, double zeta, void* S_dev, int64_t ldS, int64_t* nnz_out) {
+    if (!c || !S_dev || ldS < c->p.n2 || std::isnan(zeta)) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const ircur_params& p = c->p;
+    SparseArgs a = sparse_args(c, zeta, S_dev, ldS);
     a.nnz = nnz_out ? c->nnz : nullptr;
     if (nnz_out) HIPCHK(c, hipMemsetAsync(c->nnz, 0, sizeof(unsigned long long), c->stream));
     HIPCHK(c, launch_sparse_full(a, p.dtype, c->R, c->stream));
@@ -903,6 +909,27 @@ int ircur_time_pass(ircur_ctx* c, int32_t reps, double* us_out) {
     if (he == hipSuccess) he = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
     for (int i = 0; i < reps && he == hipSuccess; ++i) he = launch_pass(pa, c->p.dtype, c->R, c->stream);
+    if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(c, IRCUR_ERR_DEVICE, hipGetErrorString(he));
+    *us_out = 1e3 * (double)ms / reps;
+    return IRCUR_OK;
+}
+
+int ircur_time_sparse(ircur_ctx* c, double zeta, void* S_dev, int64_t ldS, int32_t reps, double* us_out) {
+    if (!c || !S_dev || ldS < c->p.n2 || std::isnan(zeta) || reps < 1 || !us_out) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const SparseArgs a = sparse_args(c, zeta, S_dev, ldS);   // no count: nothing read back per launch
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps && he == hipSuccess; ++i) he = launch_sparse_full(a, c->p.dtype, c->R, c->stream);
     if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     float ms = 0.f;

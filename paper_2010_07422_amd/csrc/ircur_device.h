@@ -166,6 +166,19 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, int blk, do
     const CF rdc = (CF)S.rowdata;
     const CI rowc = (CI)S.rows;
     F nx[U][V];                                           // next group of rows (loaded ahead)
+    // 32-bit factors: the next row's data is requested while the current row
+    // is processed (scalar loads return in any order, so the wait for the
+    // current row's data is placed before the next request); 64-bit factors
+    // would need more SGPRs than a wave has for the two rows
+    constexpr bool PF = sizeof(F) == 4;
+    constexpr int NQ = LIT ? 3 * R : 2 * R;
+    static_assert(!PF || U % 2 == 0, "the two row buffers alternate within a group");
+    F qb[2][3 * R];                                       // rows of even / odd position in a group
+    if (PF && a_end > a_begin) {
+        const CF q = rdc + (size_t)a_begin * QS;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) qb[0][c] = q[c];
+    }
     if (a_end > a_begin) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -186,10 +199,19 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, int blk, do
         for (int u = 0; u < U; ++u) {
             const int a = a0 + u;
             if (a < a_end) {
-                const CF q = rdc + (size_t)a * QS;
-                    F qa[3 * R];
+                    F* qa = qb[u & 1];
+                    if (PF) {
+                        __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0): row a's data is here
+                        __builtin_amdgcn_sched_barrier(0);
+                        const CF q = rdc + (size_t)(a + 1 < a_end ? a + 1 : a) * QS;
 #pragma unroll
-                    for (int c = 0; c < (LIT ? 3 * R : 2 * R); ++c) qa[c] = q[c];
+                        for (int c = 0; c < NQ; ++c) qb[(u + 1) & 1][c] = q[c];
+                        __builtin_amdgcn_sched_barrier(0);
+                    } else {
+                        const CF q = rdc + (size_t)a * QS;
+#pragma unroll
+                        for (int c = 0; c < NQ; ++c) qa[c] = q[c];
+                    }
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
                         const F d = v < nvalid ? dv[u][v] : F(0);

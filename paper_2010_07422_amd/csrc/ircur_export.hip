@@ -127,6 +127,173 @@ __global__ __launch_bounds__(256) void sparse_full_kernel(SparseArgs a, int64_t 
     }
 }
 
+// Full sparse part, vector form, for rows of D and S that start on lane-
+// vector boundaries: a lane covers VEC consecutive columns (one 16- or 8-byte
+// load and one store of that size per row), a wave a strip of 64 VEC columns,
+// a workgroup a band of kSpBand rows of one strip (the four waves take
+// kSpBand / 4 rows each, kSpU rows of loads in flight and the next kSpU
+// requested while the current ones are processed).  The band's factor rows
+// A_k[i, :] are staged in LDS; the lane's factor columns B_k[:, j] stay in
+// registers.  D is read and S written with non-temporal hints (each byte is
+// touched once).  Same fma chain and threshold test as every other kernel.
+// (Measured on MI355X: bands of 256 rows with 8 rows in flight beat 128 / 8,
+// 512 / 4, 512 / 8 and 256 / 16 on the 76800 x 1200 FP32 instance.)
+#ifndef IRCUR_SP_BAND
+#define IRCUR_SP_BAND 256
+#endif
+#ifndef IRCUR_SP_U
+#define IRCUR_SP_U 8
+#endif
+constexpr int kSpBand = IRCUR_SP_BAND;
+constexpr int kSpU = IRCUR_SP_U;
+
+// Lane vector of the sparse kernel: NW 32-bit words (16 or 8 bytes) holding
+// VEC elements of T.  16-byte vectors unless the lane's factor columns
+// (R x VEC values in registers) would crowd out the rows in flight.
+template <typename T, int R> struct SpLane {
+    static constexpr int NW = (R * 16 / (int)sizeof(T) <= 48) ? 4 : 2;
+    static constexpr int VEC = NW * 4 / (int)sizeof(T);
+    typedef uint32_t W __attribute__((ext_vector_type(NW)));
+};
+template <typename T, typename F, int NW> struct SpPack;
+template <int NW> struct SpPack<double, double, NW> {
+    template <typename W> __device__ static void unpack(const W& w, double* o) {
+#pragma unroll
+        for (int k = 0; k < NW / 2; ++k) o[k] = __builtin_bit_cast(double, ((uint64_t)w[2 * k + 1] << 32) | w[2 * k]);
+    }
+    template <typename W> __device__ static W pack(const double* v) {
+        W w;
+#pragma unroll
+        for (int k = 0; k < NW / 2; ++k) {
+            const uint64_t u = __builtin_bit_cast(uint64_t, v[k]);
+            w[2 * k] = (uint32_t)u;
+            w[2 * k + 1] = (uint32_t)(u >> 32);
+        }
+        return w;
+    }
+};
+template <int NW> struct SpPack<float, float, NW> {
+    template <typename W> __device__ static void unpack(const W& w, float* o) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) o[k] = __uint_as_float(w[k]);
+    }
+    template <typename W> __device__ static W pack(const double* v) {
+        W w;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[k] = __float_as_uint((float)v[k]);
+        return w;
+    }
+};
+template <int NW> struct SpPack<bf16_t, float, NW> {
+    template <typename W> __device__ static void unpack(const W& w, float* o) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            o[2 * k] = __uint_as_float(w[k] << 16);
+            o[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+        }
+    }
+    template <typename W> __device__ static W pack(const double* v) {
+        W w;
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            w[k] = (uint32_t)from_f<bf16_t>(v[2 * k]).bits | ((uint32_t)from_f<bf16_t>(v[2 * k + 1]).bits << 16);
+        return w;
+    }
+};
+
+template <typename T, typename F, int R>
+__global__ __launch_bounds__(256) void sparse_vec_kernel(SparseArgs a, int64_t nstrip) {
+    typedef SpLane<T, R> LN;
+    typedef typename LN::W W;
+    typedef SpPack<T, F, LN::NW> SV;
+    constexpr int VEC = LN::VEC;
+    constexpr int RW = kSpBand / 4;                     // rows per wave
+    __shared__ F Ab[kSpBand * R];                       // Ab[i * R + c] = A_k[i0 + i, c]
+    const int64_t strip = blockIdx.x % nstrip, band = blockIdx.x / nstrip;
+    const int64_t i0 = band * kSpBand;
+    const int nrow = (int)(a.n1 - i0 < kSpBand ? a.n1 - i0 : kSpBand);
+    const F* __restrict__ At = (const F*)a.At;
+    const F* __restrict__ B = (const F*)a.B;
+    for (int e = threadIdx.x; e < kSpBand * R; e += 256) {
+        const int c = e / kSpBand, ii = e - c * kSpBand;    // read along the rows of A_k^T
+        Ab[ii * R + c] = ii < nrow ? At[c * a.n1 + i0 + ii] : F(0);
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t j0 = (strip * 64 + lane) * VEC;
+    int nv = (int)(a.n2 - j0 < VEC ? a.n2 - j0 : VEC);
+    if (nv < 0) nv = 0;
+    const int64_t jc = nv > 0 ? j0 : 0;                 // a lane past the last column reads column 0
+    F p[R][VEC];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) p[c][v] = v < nv ? B[c * a.n2 + j0 + v] : F(0);
+    const T* __restrict__ D = (const T*)a.D;
+    T* __restrict__ S = (T*)a.S;
+    const int r0 = wave * RW;
+    const int r1 = nrow < r0 + RW ? nrow : r0 + RW;
+    uint32_t cnt = 0;
+    __syncthreads();
+    if (r1 > r0) {
+        auto load = [&](int ib, W* w) {
+#pragma unroll
+            for (int u = 0; u < kSpU; ++u) {
+                const int row = ib + u < r1 ? ib + u : r1 - 1;
+                const T* src = D + (i0 + row) * a.ldD + jc;
+                if (nv == VEC) {
+                    w[u] = __builtin_nontemporal_load((const W*)src);
+                } else {
+                    T tmp[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) tmp[v] = v < nv ? src[v] : src[0];
+                    w[u] = __builtin_bit_cast(W, tmp);
+                }
+            }
+        };
+        W nx[kSpU];
+        load(r0, nx);
+        for (int ib = r0; ib < r1; ib += kSpU) {
+            W cur[kSpU];
+#pragma unroll
+            for (int u = 0; u < kSpU; ++u) cur[u] = nx[u];
+            if (ib + kSpU < r1) load(ib + kSpU, nx);
+#pragma unroll
+            for (int u = 0; u < kSpU; ++u) {
+                const int row = ib + u;
+                if (row < r1) {
+                    F d[VEC];
+                    SV::unpack(cur[u], d);
+                    const F* q = Ab + row * R;
+                    double sv[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        F dot = F(0);
+#pragma unroll
+                        for (int c = 0; c < R; ++c) dot = fmaT(q[c], p[c][v], dot);
+                        const F x = d[v] - dot;
+                        const bool o = above(x < F(0) ? -x : x, a.zeta, a.zeta_f);
+                        cnt += (o && v < nv) ? 1u : 0u;
+                        sv[v] = o ? (double)x : 0.0;
+                    }
+                    T* dst = S + (i0 + row) * a.ldS + j0;
+                    if (nv == VEC) {
+                        __builtin_nontemporal_store(SV::template pack<W>(sv), (W*)dst);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v)
+                            if (v < nv) dst[v] = from_f<T>(sv[v]);
+                    }
+                }
+            }
+        }
+    }
+    if (a.nnz) {
+        for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+        if (lane == 0 && cnt) atomicAdd(a.nnz, (unsigned long long)cnt);
+    }
+}
+
 template <typename T, typename F, int R>
 hipError_t cur_r(const CurArgs& a, hipStream_t s) {
     if (a.Rout || a.SI) {
@@ -142,6 +309,16 @@ hipError_t cur_r(const CurArgs& a, hipStream_t s) {
 
 template <typename T, typename F, int R>
 hipError_t sparse_r(const SparseArgs& a, hipStream_t s) {
+    constexpr int VEC = SpLane<T, R>::VEC;
+    constexpr int LB = SpLane<T, R>::NW * 4;       // bytes per lane and row
+    const bool aligned = ((uintptr_t)a.D % LB) == 0 && ((uintptr_t)a.S % LB) == 0 &&
+                         (a.ldD * (int64_t)sizeof(T)) % LB == 0 && (a.ldS * (int64_t)sizeof(T)) % LB == 0;
+    if (aligned && R * VEC <= 96) {
+        const int64_t nstrip = (a.n2 + 64 * VEC - 1) / (64 * VEC), nband = (a.n1 + kSpBand - 1) / kSpBand;
+        if (nstrip * nband > 0x7fffffffLL) return hipErrorInvalidValue;
+        sparse_vec_kernel<T, F, R><<<(unsigned)(nstrip * nband), 256, 0, s>>>(a, nstrip);
+        return hipGetLastError();
+    }
     const int64_t ncb = (a.n2 + 255) / 256, nb = (a.n1 + kSparseRows - 1) / kSparseRows;
     if (ncb * nb > 0x7fffffffLL) return hipErrorInvalidValue;
     sparse_full_kernel<T, F, R><<<(unsigned)(ncb * nb), 256, 0, s>>>(a, ncb);

@@ -57,6 +57,27 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// LDS view of a pointer into the kernel's shared memory: helpers that are not
+// inlined receive generic pointers, and generic (flat) accesses are slower
+// than LDS ones and hold up the waits for other memory results.
+typedef __attribute__((address_space(3))) double ldouble;
+__device__ __forceinline__ ldouble* lp(double* p) { return (ldouble*)p; }
+__device__ __forceinline__ const ldouble* lp(const double* p) { return (const ldouble*)p; }
+
+// 1/sqrt(d) for a positive normal d: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - d y^2) / 2 (each doubles the correct bits; the
+// result is within an ulp or two of the rounded value).  Shorter in dependent
+// operations than a correctly rounded square root followed by a division.
+__device__ __forceinline__ double rsqrt_d(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = __builtin_fma(-d * y, y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // ------------------------------------------------------- MFMA (FP64) ---
 // One 16 x 16 output tile, acc += op(A) op(B) over k in [k0, k1) (multiples
 // of 4), operands in LDS.  Operand layout of v_mfma_f64_16x16x4f64: lane l
@@ -147,90 +168,83 @@ __device__ void mm_small(const double* A, int lda, const double* B, int ldb, dou
 
 // ------------------------------------------------ small factorisations ---
 // Cholesky G = L L^T of a P x P symmetric positive semidefinite matrix and
-// Linv = L^-1, by the first wave with the P x P elements spread over its 64
-// lanes: lane l holds element (i, k) = (l / P + (64 / P) q, l % P) for
-// q < P * P / 64.  Step j of the factorisation forms column j of L in the
-// lanes that hold it and publishes it in LDS (in the order in which each lane
-// reads its rows); every lane then updates its trailing elements.  The inverse
-// (forward elimination on [L | I]) publishes each finished row the same way.
-// One wave: its LDS operations complete in program order, and a wave barrier
-// keeps the compiler from moving a lane's reads above the other lanes'
-// writes.  The only register reads across lanes are the P pivots, in uniform
-// control flow.  A pivot <= tol * max_j G_jj marks a dependent direction: its
-// column of L and row of Linv are zero and dead[j] = 1.  G, L, Linv are P x P
-// in LDS (L and Linv also serve as the exchange buffers).
+// Linv = L^-1, by the first wave: lane i holds row i of the trailing matrix
+// (row i of L once factored) and column i of Linv.  Step j takes the pivot
+// from lane j, scales column j, and publishes it in LDS (one write per lane,
+// one broadcast read of the column per lane); with L[k][j] every lane applies
+// the rank-1 update a[i][k] -= L[i][j] L[k][j] (k > j) and the forward
+// elimination of column j of [L | I] on its column of Linv (x[j] *= 1/L[j][j],
+// then x[k] -= L[k][j] x[j]).  One LDS round trip per step; the wave's LDS
+// operations complete in program order and a wave barrier keeps the compiler
+// from moving a lane's reads above the other lanes' writes.  The steps carry
+// no lane-dependent selects: the entries above the diagonal of a finished row
+// go on being updated but are never read, and the diagonal (the pivot) is
+// kept in LDS and put in place when L is stored.  The whole wave runs every
+// step (lanes >= P shadow row P - 1 and store nothing).  A pivot <= tol *
+// max_j G_jj marks a dependent direction: its column of L and row of Linv are
+// zero and dead[j] = 1.  G, L, Linv are P x P in LDS; L serves as the
+// exchange buffer and the diagonal of Linv holds the pivots until the end, so
+// G may alias neither.
 template <int P>
-__device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, double tol) {
-    static_assert(64 % P == 0 && P >= 8, "P must divide 64");
-    constexpr int RPL = 64 / P;          // rows covered by one q step
-    constexpr int NQ = P * P / 64;       // elements per lane
+__device__ __forceinline__ void chol_inv(const double* G_, double* L_, double* Linv_, int* dead, double tol,
+                                         int live = P) {
+    static_assert(P >= 2 && P <= 64 && P % 2 == 0, "one wave holds the P rows");
+    const ldouble* G = lp(G_);
+    ldouble* L = lp(L_);
+    ldouble* Linv = lp(Linv_);
     if (threadIdx.x < 64) {
         const int l = threadIdx.x;
-        const int i0 = l / P, k = l % P;
-        double a[NQ];
+        const int i = l < P ? l : P - 1;    // row of the trailing matrix and of L, column of Linv
+        double a[P], x[P];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) a[q] = G[(i0 + RPL * q) * P + k];
+        for (int k = 0; k < P; ++k) {
+            a[k] = G[i * P + k];
+            x[k] = (k == i) ? 1.0 : 0.0;
+        }
         double dmax = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) dmax = fmax(dmax, readlane_d(a[j / RPL], j + P * (j % RPL)));
+        for (int j = 0; j < P; ++j) dmax = fmax(dmax, readlane_d(a[j], j));
         const double thr = tol * dmax;
-        double inv_d[P];
-        double* colbuf = Linv;           // row j: column j of L, entry (i % RPL) * NQ + i / RPL
+        ldouble* col = L;                   // row j of the buffer: column j of L
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            const double d = readlane_d(a[j / RPL], j + P * (j % RPL));
-            const bool dj = !(d > thr);
-            const double piv = dj ? 0.0 : __builtin_sqrt(d);
-            const double inv = dj ? 0.0 : 1.0 / piv;
-            inv_d[j] = inv;
-            if (k == j) {
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const int i = i0 + RPL * q;
-                    const double lij = (i > j) ? a[q] * inv : ((i == j) ? piv : 0.0);
-                    a[q] = lij;
-                    colbuf[j * P + i0 * NQ + q] = lij;
+            if (j >= live) {                // a column known to be zero: dead without a step
+                if (l == 0) {
+                    dead[j] = 1;
+                    Linv[j * P + j] = 0.0;
                 }
+                continue;
             }
-            __builtin_amdgcn_wave_barrier();     // keep the other lanes' reads after these writes
-            double li[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) li[q] = colbuf[j * P + i0 * NQ + q];
-            const double lk = colbuf[j * P + (k % RPL) * NQ + k / RPL];
-            if (k > j) {
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    if (i0 + RPL * q >= k) a[q] = __builtin_fma(-li[q], lk, a[q]);
-            }
-            if (l == 0) dead[j] = dj ? 1 : 0;
-        }
-        // Linv by forward elimination on [L | I]: row m is final once the rows
-        // above it have been subtracted; it is published and subtracted below
-        double x[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) x[q] = (i0 + RPL * q == k) ? 1.0 : 0.0;
-        double* rowbuf = L;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            if (i0 == m % RPL) {
-                x[m / RPL] *= inv_d[m];
-                rowbuf[m * P + k] = x[m / RPL];
+            const double d = readlane_d(a[j], j);
+            const bool dj = !(d > thr);
+            const double inv = dj ? 0.0 : rsqrt_d(d);
+            const double piv = dj ? 0.0 : d * inv;
+            a[j] *= inv;                    // L[i][j] for i > j
+            x[j] *= inv;
+            col[j * P + i] = a[j];          // the shadow lanes write row P - 1's value
+            if (l == 0) {
+                dead[j] = dj ? 1 : 0;
+                Linv[j * P + j] = piv;
             }
             __builtin_amdgcn_wave_barrier();
-            double lm[NQ];
+            double lk[P];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) lm[q] = colbuf[m * P + i0 * NQ + q];
-            const double xm = rowbuf[m * P + k];
+            for (int k = j + 1; k < P; ++k) lk[k] = col[j * P + k];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
-                if (i0 + RPL * q > m) x[q] = __builtin_fma(-lm[q], xm, x[q]);
+            for (int k = j + 1; k < P; ++k) {
+                a[k] = __builtin_fma(-a[j], lk[k], a[k]);
+                x[k] = __builtin_fma(-lk[k], x[j], x[k]);
+            }
         }
-        __builtin_amdgcn_wave_barrier();         // the buffers are overwritten below
+        __builtin_amdgcn_wave_barrier();    // the buffers are overwritten below
+        const double pii = Linv[i * P + i];
+        __builtin_amdgcn_wave_barrier();
+        if (l < P) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = i0 + RPL * q;
-            L[i * P + k] = (k <= i) ? a[q] : 0.0;
-            Linv[i * P + k] = (k <= i) ? x[q] : 0.0;
+            for (int k = 0; k < P; ++k) {
+                L[i * P + k] = (k < i && k < live) ? a[k] : ((k == i) ? pii : 0.0);
+                Linv[k * P + i] = (i <= k && k < live) ? x[k] : 0.0;
+            }
         }
     }
     __syncthreads();
@@ -245,7 +259,7 @@ __device__ void chol_inv(const double* G, double* L, double* Linv, int* dead, do
 // is refilled with pseudo-random entries and the pass repeated; columns at or
 // past `live` stay zero.
 template <int P>
-__device__ int orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
+__device__ __forceinline__ int orthonormalise(double* X, int m16, int rows_valid, int live, double* Gs, double* Ls,
                               double* Li, int* dead, double* scratch, double* red, uint64_t salt,
                               int passes = 4) {
     int maxp = passes;
@@ -266,7 +280,7 @@ __device__ int orthonormalise(double* X, int m16, int rows_valid, int live, doub
             __syncthreads();
             if (!(dmax > 1e-13)) break;
         }
-        chol_inv<P>(Gs, Ls, Li, dead, 1e-14);
+        chol_inv<P>(Gs, Ls, Li, dead, 1e-14, live);
         ++done;
         mm_rows<P, false, true>(X, P, Li, P, X, P, m16, P, rows_valid);
         __syncthreads();

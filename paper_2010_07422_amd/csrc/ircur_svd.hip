@@ -357,7 +357,7 @@ __device__ __forceinline__ void svd_body(const SvdArgs& a, const int wg) {
     // ---- epilogue ---------------------------------------------------------
     // Gy = Ly Ly^T; pivots below ptol * max are dropped (pinv rule on sigma^2)
     const double ptol = 4.0 * (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
-    chol_inv<P>(Gy, Ls, Li, dead, ptol);
+    chol_inv<P>(Gy, Ls, Li, dead, ptol, r);   // columns >= r of Y are zero
     mm_rows<P, false, true>(Y, P, Li, P, Wb, P, bs16, P, nb);     // Wt = Y Ly^-T (this block)
     // Gamma = Ly^-1 H;  TA = Ly^-T;  Kc = Ly^T  (r x r, one entry per thread)
     for (int e = tid; e < P * P; e += NT) {
@@ -702,7 +702,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
 
     // ---- epilogue ---------------------------------------------------------
     const double ptol = 4.0 * (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
-    chol_inv<P>(Gy, Ls, Li, dead, ptol);
+    chol_inv<P>(Gy, Ls, Li, dead, ptol, r);   // columns >= r of Y are zero
     mm_rows<P, false, true>(Y, P, Li, P, Wb, P, bs16, P, nb);     // Wt = Y Ly^-T (this block)
     for (int e = tid; e < P * P; e += NT) {
         const int i = e / P, j = e - i * P;

@@ -73,6 +73,7 @@ _SIGS = {
     "ircur_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ircur_get_timing": (ctypes.c_int, [_P, _DP, ctypes.POINTER(ctypes.c_int64)]),
     "ircur_time_pass": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),
+    "ircur_time_sparse": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, _DP]),
     "ircur_get_info": (ctypes.c_int, [_P, _I32P, _DP, _DP, _I32P]),
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
@@ -347,6 +348,18 @@ class IRCUR:
         launched `reps` times back to back between two HIP events."""
         us = ctypes.c_double()
         self._check(lib().ircur_time_pass(self.h, int(reps), ctypes.byref(us)), "ircur_time_pass")
+        return us.value
+
+    def time_sparse(self, S, zeta=-1.0, reps=10):
+        """Mean duration in microseconds of the full sparse-part extraction
+        into S (an n1 x n2 tensor of D's dtype), launched `reps` times back to
+        back between two HIP events."""
+        n1, n2 = self.p.n1, self.p.n2
+        if S.dim() != 2 or S.shape != (n1, n2) or S.stride(1) != 1 or S.dtype != self.D.dtype:
+            raise ValueError("S must be an n1 x n2 tensor of D's dtype with unit column stride")
+        us = ctypes.c_double()
+        self._check(lib().ircur_time_sparse(self.h, float(zeta), ctypes.c_void_p(S.data_ptr()), S.stride(0),
+                                            int(reps), ctypes.byref(us)), "ircur_time_sparse")
         return us.value
 
     def phase_profile(self):

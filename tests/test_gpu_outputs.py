@@ -113,6 +113,49 @@ def test_sparse_full_matches_threshold_of_factors(dtname):
     ctx.close()
 
 
+@pytest.mark.parametrize("dtname", ["f64", "f32", "bf16"])
+def test_sparse_full_strided_and_ragged(dtname):
+    """Rows of D and S with a padded stride (16-byte aligned rows, a last
+    vector of the row cut short: the vector kernel with its ragged tail) and
+    with an unpadded odd stride (rows off 16-byte boundaries: the per-element
+    kernel); both against the threshold of D - A_k B_k."""
+    torch = require_gpu()
+    from paper_2010_07422_amd.ircur import IRCUR
+    dtype = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtname]
+    n1, n2, ld, r = 300, 1003, 1008, 4
+    p = synth.planted(n1, n2, r, 0.1, seed=21)
+    print(f"case sparse_full strided {dtname} n1={n1} n2={n2} ld={ld}", flush=True)
+    big = torch.zeros((n1, ld), dtype=torch.float64, device="cuda")
+    big[:, :n2] = torch.tensor(p.D, dtype=torch.float64, device="cuda")
+    Dpad = big.to(dtype)[:, :n2]
+    assert Dpad.stride(0) == ld
+    ctx = IRCUR(Dpad, r, 60, 60, p.Lmax, gamma=0.7, eps=0.0, max_iter=12, seed=3, resample=True)
+    ctx.solve()
+    A, B = factors_np(ctx)
+    Dh = Dpad.double().cpu().numpy()
+    X = Dh - A @ B
+    z = 1e-3 * p.Lmax
+    ref = O.hard_threshold(X, z)
+    band = np.abs(np.abs(X) - z) <= (1e-12 if dtname == "f64" else 1e-4) * np.abs(Dh).max()
+    rt = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}[dtname]
+    Spad = torch.full((n1, ld), 7.0, dtype=dtype, device="cuda")
+    for out in (Spad[:, :n2], None):
+        S, nnz = ctx.sparse_full(z, out=out)
+        Sh = S.double().cpu().numpy()
+        assert np.array_equal((Sh != 0)[~band], (ref != 0)[~band])
+        assert nnz == int(np.count_nonzero(Sh))
+        keep = (Sh != 0) & (ref != 0)
+        assert np.allclose(Sh[keep], ref[keep], rtol=rt, atol=rt * np.abs(Dh).max() * 1e-2)
+    # the padding columns of the output rows are left untouched
+    assert bool((Spad[:, n2:] == 7.0).all())
+    # timed relaunches (no count) rewrite the same values
+    S0 = Spad[:, :n2].clone()
+    us = ctx.time_sparse(Spad[:, :n2], z, reps=3)
+    assert us > 0.0
+    assert torch.equal(Spad[:, :n2], S0)
+    ctx.close()
+
+
 @pytest.mark.parametrize("dtname", ["f64", "f32"])
 def test_to_svd_matches_dense_svd(dtname):
     torch = require_gpu()
