@@ -58,8 +58,37 @@ __device__ void grid_barrier(uint32_t* ctr, uint32_t target, int32_t* fail) {
     __syncthreads();
 }
 
-// Sum of G partials (stride apart) in a fixed order, loads issued together.
-template <int G>
+// Device-scope (all XCDs) stores and loads of the data that workgroups of
+// one launch exchange across a grid barrier: written through to, and read
+// from, the device-coherent level, so the barrier itself needs no cache-wide
+// fence.
+__device__ __forceinline__ void st_dev(gdouble* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const gdouble* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for data exchanged with st_dev / ld_dev: every thread's stores
+// have completed before the workgroup is counted, and the loads that follow
+// read the device-coherent level.
+__device__ void grid_barrier_dev(uint32_t* ctr, uint32_t target, int32_t* fail) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > (1u << 22)) { __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break; }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// Sum of G partials (stride apart) in a fixed order, loads issued together
+// (DEV: device-scope loads, for partials written with st_dev in this launch).
+template <int G, bool DEV = false>
 __device__ __forceinline__ void reduce_parts(const gdouble* __restrict__ src, size_t stride, int total,
                                              double* out) {
     constexpr int E = G <= 8 ? 7 : (G <= 16 ? 3 : 1);   // elements per thread per batch (<= 63 loads)
@@ -69,7 +98,8 @@ __device__ __forceinline__ void reduce_parts(const gdouble* __restrict__ src, si
         for (int q = 0; q < E; ++q) {
             const int e = e0 + q * NT;
 #pragma unroll
-            for (int g = 0; g < G; ++g) v[q][g] = (e < total) ? src[(size_t)g * stride + e] : 0.0;
+            for (int g = 0; g < G; ++g)
+                v[q][g] = (e < total) ? (DEV ? ld_dev(src + (size_t)g * stride + e) : src[(size_t)g * stride + e]) : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < E; ++q) {
@@ -646,7 +676,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
                         if (k0 + u < nks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], yv[u], acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Zp[(size_t)(16 * tj + (l64 >> 4) + 4 * v) * P + (l64 & 15)] = acc[v];
+                for (int v = 0; v < 4; ++v) st_dev(Zp + (size_t)(16 * tj + (l64 >> 4) + 4 * v) * P + (l64 & 15), acc[v]);
             }
         }
         mm_small<P, true, false>(Y, P, Y, P, Gy, bs16, scr);
@@ -654,17 +684,17 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         {
             gdouble* Gp = gp(a.Gp) + (size_t)wg * 2 * P * P;
             for (int e = tid; e < P * P; e += NT) {
-                Gp[e] = Gy[e];
-                Gp[P * P + e] = H[e];
+                st_dev(Gp + e, Gy[e]);
+                st_dev(Gp + P * P + e, H[e]);
             }
         }
         PHASE(3);
         ++nbar;
-        grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        grid_barrier_dev(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
         PHASE(4);
         // reduce-scatter: full Gy and H, this workgroup's slice of Z
-        reduce_parts<G>(gp(a.Gp), (size_t)2 * P * P, 2 * P * P, Gy);
-        reduce_parts<G>(gp(Zp_all) + (size_t)z0 * P, (size_t)sJ16 * P, zn * P, Zs);
+        reduce_parts<G, true>(gp(a.Gp), (size_t)2 * P * P, 2 * P * P, Gy);
+        reduce_parts<G, true>(gp(Zp_all) + (size_t)z0 * P, (size_t)sJ16 * P, zn * P, Zs);
         __syncthreads();
         // residual of the slice: ||Z - Q Gy||^2 over rows z0 .. z1
         double part = 0.0;
@@ -676,24 +706,24 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
             const double dz = Zs[e] - q;
             part = __builtin_fma(dz, dz, part);
         }
-        for (int e = tid; e < zn * P; e += NT) gp(a.Zr)[(size_t)z0 * P + e] = Zs[e];
+        for (int e = tid; e < zn * P; e += NT) st_dev(gp(a.Zr) + (size_t)z0 * P + e, Zs[e]);
         const double num_s = block_sum(part, red);
-        if (tid == 0) gp(a.rp)[wg] = num_s;
+        if (tid == 0) st_dev(gp(a.rp) + wg, num_s);
         PHASE(5);
         ++nbar;
-        grid_barrier(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        grid_barrier_dev(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
         double gn = 0.0;
         for (int e = tid; e < P * P; e += NT) gn = __builtin_fma(Gy[e], Gy[e], gn);
         const double den = block_sum(gn, red);
         double num = 0.0;
-        for (int g = 0; g < G; ++g) num += gp(a.rp)[g];
+        for (int g = 0; g < G; ++g) num += ld_dev(gp(a.rp) + g);
         rho = den > 0.0 ? __builtin_sqrt(num / den) : 0.0;
         ++it;
         conv = !(rho > tol_k);
         PHASE(6);
         if (conv || it >= a.max_it) break;
         // all-gather: Q <- orth(Z)
-        batched(sJ16 * P, [&](int e) { return e < sJ * P ? gp(a.Zr)[e] : 0.0; }, [&](int e, double v) { Q[e] = v; });
+        batched(sJ16 * P, [&](int e) { return e < sJ * P ? ld_dev(gp(a.Zr) + e) : 0.0; }, [&](int e, double v) { Q[e] = v; });
         __syncthreads();
         orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red,
                           a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
