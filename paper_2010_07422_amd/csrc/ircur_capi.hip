@@ -136,6 +136,8 @@ struct ircur_ctx {
     uint32_t* pcnt = nullptr;          // per-tile tickets (zero between launches)
     DevState* st = nullptr;
     DevState* st_host = nullptr;   // pinned
+    DevState* snap_host = nullptr; // pinned, 2: the state after each of two chunks in flight (solve)
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
     SvdInfo* info = nullptr;       // max_iter records
     double* hist = nullptr;        // max_iter
     int32_t k = 0;                 // completed iterations (host view after sync)
@@ -236,11 +238,14 @@ void free_all(ircur_ctx* c) {
     if (c->Ipin) (void)hipHostFree(c->Ipin);
     if (c->Jpin) (void)hipHostFree(c->Jpin);
     if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->ev_made)
         for (int i = 0; i < kRing; ++i)
             for (int j = 0; j < 5; ++j) (void)hipEventDestroy(c->ev[i][j]);
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h) {
         if (c->h2d[h]) (void)hipEventDestroy(c->h2d[h]);
+        if (c->snap_ev[h]) (void)hipEventDestroy(c->snap_ev[h]);
+    }
 }
 
 double zeta_at(const ircur_params& p, int k) { return p.zeta0 * std::pow(p.gamma, (double)k); }
@@ -548,14 +553,17 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     TRY(dalloc(c, &c->Idev, (size_t)kRing * (p.sI + kIndexPad)));
     TRY(dalloc(c, &c->Jdev, (size_t)kRing * (p.sJ + kIndexPad)));
     if (hipEventCreateWithFlags(&c->h2d[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->h2d[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->h2d[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->snap_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->snap_ev[1], hipEventDisableTiming) != hipSuccess) {
         free_all(c);
         delete c;
         return IRCUR_ERR_DEVICE;
     }
     if (hipHostMalloc((void**)&c->Ipin, sizeof(int32_t) * kRing * (p.sI + kIndexPad), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->Jpin, sizeof(int32_t) * kRing * (p.sJ + kIndexPad), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->snap_host, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
         free_all(c);
         delete c;
         return IRCUR_ERR_ALLOC;
@@ -686,17 +694,38 @@ int ircur_solve(ircur_ctx* c, int32_t* iters_out, double* e_out) {
     const ircur_params& p = c->p;
     int rc0 = read_state(c);
     if (rc0) return rc0;
+    // Two chunks in flight: the next chunk is sampled and enqueued while the
+    // device runs the current one, and the host waits only for a copy of the
+    // device state taken after the older chunk.  Iterations enqueued past the
+    // device-side stop return at once; chunks stay small (up to kSolveChunk)
+    // so that few are enqueued past the stop.
+    constexpr int kSolveChunk = 8;
     int chunk = 2;
-    while (!c->stopped && c->k < p.max_iter) {
-        const int n = std::min(chunk, p.max_iter - c->k_enq);
-        int rc = enqueue_chunk(c, n, nullptr, nullptr);
-        if (rc) return rc;
-        rc = read_state(c);
-        if (rc) return rc;
-        rc = status_after(c);
-        if (rc) return rc;
-        chunk = std::min(chunk * 2, kChunk);
+    int inflight = 0, oldest = 0;
+    bool seen_stop = c->stopped;
+    while (true) {
+        while (inflight < 2 && !seen_stop && c->k_enq < p.max_iter) {
+            const int n = std::min(chunk, p.max_iter - c->k_enq);
+            int rc = enqueue_chunk(c, n, nullptr, nullptr);
+            if (rc) return rc;
+            const int slot = (oldest + inflight) & 1;
+            HIPCHK(c, hipMemcpyAsync(c->snap_host + slot, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipEventRecord(c->snap_ev[slot], c->stream));
+            ++inflight;
+            chunk = std::min(chunk * 2, kSolveChunk);
+        }
+        if (inflight == 0) break;
+        HIPCHK(c, hipEventSynchronize(c->snap_ev[oldest]));
+        const DevState& sn = c->snap_host[oldest];
+        oldest ^= 1;
+        --inflight;
+        if (sn.stop || sn.svd_fail || sn.nonfinite || sn.k_done >= p.max_iter) seen_stop = true;
+        if (seen_stop) break;
     }
+    int rc = read_state(c);   // waits for the chunk still in flight (no-ops past the stop)
+    if (rc) return rc;
+    rc = status_after(c);
+    if (rc) return rc;
     if (iters_out) *iters_out = c->k;
     const double e = c->k > 0 ? c->st_host->e_last : 1.0;
     if (e_out) *e_out = e;
