@@ -129,7 +129,10 @@ int ircur_sync(ircur_ctx* ctx, int32_t* k_out, double* e_out);
 /*
  * Run Algorithm 1 to the stop rule (e_k <= eps) or max_iter.  Writes the
  * number of iterations and the last e.  Returns IRCUR_OK or
- * IRCUR_NOT_CONVERGED (both with a valid result), or an error.
+ * IRCUR_NOT_CONVERGED (both with a valid result), or an error.  Iterations
+ * are enqueued in chunks, two in flight; iterations enqueued past the
+ * device-side stop return at once and change nothing.  Synchronises (returns
+ * once every enqueued launch has finished).
  */
 int ircur_solve(ircur_ctx* ctx, int32_t* iters_out, double* e_out);
 
