@@ -241,3 +241,32 @@ def test_time_pass_leaves_the_run_unchanged():
     assert ctx.history() == ctx2.history()
     ctx.close()
     ctx2.close()
+
+
+@pytest.mark.parametrize("eps,max_iter", [(1e-5, 100), (1e-3, 100), (0.0, 3), (0.0, 11), (1e-5, 1)])
+def test_solve_stops_where_single_steps_stop(eps, max_iter):
+    """ircur_solve (chunks enqueued two at a time, iterations past the device
+    stop are no-ops) ends at the same iteration, with the same e history and
+    the same factors bit for bit, as single steps stopped by the host."""
+    torch = require_gpu()
+    n, r = 1000, 5
+    p = synth.planted(n, n, r, 0.1, seed=31)
+    s = synth.sample_size(4, r, n)
+    print(f"case solve vs steps eps={eps} max_iter={max_iter}", flush=True)
+    a, Dd = _ctx(torch, p.D.astype(np.float32), torch.float32, r, s, s, p.Lmax, gamma=0.7, eps=eps,
+                 max_iter=max_iter, seed=5, resample=True)
+    it, e, rc = a.solve()
+    b, _ = _ctx(torch, Dd, None, r, s, s, p.Lmax, gamma=0.7, eps=eps, max_iter=max_iter, seed=5, resample=True)
+    k = 0
+    while k < max_iter:
+        eb = b.step()
+        k += 1
+        if eb <= eps:
+            break
+    assert it == k
+    assert a.history() == b.history()
+    Aa, Ba = factors_np(a)
+    Ab, Bb = factors_np(b)
+    assert np.array_equal(Aa, Ab) and np.array_equal(Ba, Bb)
+    a.close()
+    b.close()
