@@ -83,9 +83,10 @@ __device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
 // Rows in flight per wave (the next group is loaded while the current one is
 // processed), columns per lane and waves per workgroup, by storage type.
 // (Measured on MI355X at n = 10^4: FP64 is fastest with 8 waves, BF16 and
-// FP32 with 4 waves and one column per lane.)
+// FP32 with 4 waves and one column per lane; BF16 with 32 rows in flight,
+// which covers a wave's share of a 128-row block in one group.)
 template <typename T> struct RowsInFlight { static constexpr int value = 8; };
-template <> struct RowsInFlight<bf16_t> { static constexpr int value = 16; };
+template <> struct RowsInFlight<bf16_t> { static constexpr int value = 32; };
 template <> struct RowsInFlight<double> { static constexpr int value = 8; };
 template <typename T> struct ColsPerLane { static constexpr int value = 1; };
 template <typename T, int R> struct PassWaves { static constexpr int value = 4; };
