@@ -256,6 +256,19 @@ int ircur_get_info(ircur_ctx* ctx, int32_t* svd_iters, double* svd_resid,
                    double* gap, int32_t* kept);
 
 /*
+ * Per-iteration record of the top-r SVD of the core (section 3.1), for the
+ * iterations completed since ircur_init, ircur_reset, ircur_set_factors or
+ * ircur_set_state (entry i is iteration k_0 + i + 1): subspace iterations
+ * used, the Ritz estimate of sigma_{r+1} / sigma_r (the gap that decides
+ * whether H_r is unique; -1 when the subspace block holds no column beyond r)
+ * and the number of components kept by the pseudo-inverse rule.  Host arrays
+ * of `cap` entries, any of them NULL; *n_out = entries written.
+ * Synchronises.
+ */
+int ircur_get_svd_history(ircur_ctx* ctx, int32_t* iters_host, double* gap_host,
+                          int32_t* kept_host, int32_t cap, int32_t* n_out);
+
+/*
  * The sampler, on the host (no device needed): index sets of stream t.
  * Generator: SplitMix64 (Steele, Lea, Flood 2014) started from
  * mix(seed xor ((t+1) * 0xD1B54A32D192ED03)); bounded draws by 128-bit

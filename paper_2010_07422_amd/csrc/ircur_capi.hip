@@ -898,6 +898,26 @@ int ircur_get_info(ircur_ctx* c, int32_t* svd_iters, double* svd_resid, double* 
     return IRCUR_OK;
 }
 
+int ircur_get_svd_history(ircur_ctx* c, int32_t* iters_host, double* gap_host, int32_t* kept_host,
+                          int32_t cap, int32_t* n_out) {
+    if (!c || cap < 0 || (cap > 0 && !iters_host && !gap_host && !kept_host)) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    const int first = c->k_base, n = std::min(cap, c->k - c->k_base);
+    if (n > 0) {
+        std::vector<SvdInfo> h((size_t)n);
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->info + first, sizeof(SvdInfo) * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int i = 0; i < n; ++i) {
+            if (iters_host) iters_host[i] = h[i].iters;
+            if (gap_host) gap_host[i] = h[i].gap;
+            if (kept_host) kept_host[i] = h[i].kept;
+        }
+    }
+    if (n_out) *n_out = n > 0 ? n : 0;
+    return IRCUR_OK;
+}
+
 int ircur_set_timing(ircur_ctx* c, int32_t enable) {
     if (!c) return IRCUR_ERR_ARG;
     int rc = read_state(c);

@@ -75,6 +75,7 @@ _SIGS = {
     "ircur_time_pass": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),
     "ircur_time_sparse": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.c_int32, _DP]),
     "ircur_get_info": (ctypes.c_int, [_P, _I32P, _DP, _DP, _I32P]),
+    "ircur_get_svd_history": (ctypes.c_int, [_P, _I32P, _DP, _I32P, ctypes.c_int32, _I32P]),
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
     "ircur_get_phase_profile": (ctypes.c_int, [_P, _DP]),
@@ -322,6 +323,20 @@ class IRCUR:
         self._check(lib().ircur_get_info(self.h, ctypes.byref(it), ctypes.byref(res), ctypes.byref(gap),
                                          ctypes.byref(kept)), "ircur_get_info")
         return Info(it.value, res.value, gap.value, kept.value)
+
+    def svd_history(self):
+        """Per completed iteration: (subspace iterations, Ritz gap estimate
+        sigma_{r+1}/sigma_r or -1, kept components), as three lists."""
+        cap = self.p.max_iter
+        it = np.zeros(cap, np.int32)
+        gap = np.zeros(cap, np.float64)
+        kept = np.zeros(cap, np.int32)
+        n = ctypes.c_int32()
+        self._check(lib().ircur_get_svd_history(self.h, it.ctypes.data_as(_I32P), gap.ctypes.data_as(_DP),
+                                                kept.ctypes.data_as(_I32P), cap, ctypes.byref(n)),
+                    "ircur_get_svd_history")
+        m = n.value
+        return it[:m].tolist(), gap[:m].tolist(), kept[:m].tolist()
 
     def get_state(self) -> bytes:
         n = ctypes.c_size_t()

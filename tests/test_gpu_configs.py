@@ -2,10 +2,8 @@
 
 - n = 3000, r = 5, FP32: to e <= 1e-5 against the FP64 oracle on the same
   (float-rounded) D and index sets, <= 1e-5;
-- n = 10^4, r = 10, D in BF16: against an FP64 GPU run on the same D, for L
-  (factored difference) and S (sampled blocks), <= 1e-2; reaches e <= 1e-5;
-- 76800 x 1200 video stand-in, r = 2, |I| = 800, |J| = 200, FP32: against the
-  FP64 oracle at the final iteration, <= 1e-5, and sampled entries of L;
+- (the n = 10^4 BF16/FP64 and video workloads are compared with the oracle
+  in test_gpu_northstar.py)
 - edge cases: |I| = n1 and |J| = n2 (CUR of the whole matrix), r = 1,
   zeta_0 = 0, exact low rank, a NaN in D, resume from a checkpoint, IRCUR-F,
   err_mode 1, bitwise repeatability.
@@ -44,80 +42,6 @@ def test_planted_n3000_r5_f32_against_oracle():
     d = O.factored_rel_diff(A, B, ref.A, ref.B)
     print("iters", it, "e", e, "diff vs oracle", d, "vs truth", O.factored_rel_diff(A, B, p.W, p.V.T), flush=True)
     assert e <= 1e-5 and d <= 1e-5
-    ctx.close()
-
-
-def test_planted_n10000_r10_bf16_against_f64_gpu():
-    torch = require_gpu()
-    cfg = synth.CONFIGS["planted_n10000_r10_bf16"]
-    n, r = cfg["n"], cfg["r"]
-    p = synth.planted(n, n, r, cfg["alpha"], seed=cfg["data_seed"])
-    s = synth.sample_size(cfg["c"], r, n)
-    print("case n=10000 r=10 bf16 vs f64", flush=True)
-    D64 = to_dev(torch, p.D, torch.float64)
-    out = {}
-    for name, D in (("bf16", D64.to(torch.bfloat16)), ("f64", D64)):
-        ctx, _ = _ctx(torch, D, None, r, s, s, p.Lmax, gamma=cfg["gamma"], eps=cfg["eps"],
-                      max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
-        it, e, rc = ctx.solve()
-        A, B = factors_np(ctx)
-        cur = ctx.cur()
-        out[name] = (A, B, it, e, cur["S_I"].double().cpu().numpy(), cur["I"])
-        ctx.close()
-        del D
-    A1, B1, it1, e1, S1, I1 = out["bf16"]
-    A0, B0, it0, e0, S0, I0 = out["f64"]
-    dL = O.factored_rel_diff(A1, B1, A0, B0)
-    print("bf16 iters", it1, "e", e1, "f64 iters", it0, "e", e0, "L diff", dL, flush=True)
-    assert e1 <= 1e-5 and e0 <= 1e-5
-    assert dL <= 1e-2
-    # S on the sampled rows of the bf16 run's last iteration, against the FP64
-    # estimate thresholded on the same rows
-    Dh = p.D[I1, :]
-    S_ref = O.hard_threshold(Dh - A0[I1, :] @ B0, cfg_zeta(p, cfg, it1))
-    dS = np.linalg.norm(S1 - S_ref) / np.linalg.norm(S_ref)
-    print("S diff", dS, flush=True)
-    assert dS <= 1e-2
-
-
-def cfg_zeta(p, cfg, it):
-    return p.Lmax * cfg["gamma"] ** (it - 1)
-
-
-def test_video_76800x1200_f32():
-    torch = require_gpu()
-    cfg = synth.CONFIGS["video_76800x1200_r2_f32"]
-    v = synth.video(cfg["h"], cfg["w"], cfg["frames"], seed=cfg["data_seed"])
-    Lmax = float(np.abs(v.F @ v.G.T).max())
-    r, sI, sJ = cfg["r"], cfg["sI"], cfg["sJ"]
-    print("case video 76800x1200", flush=True)
-    ctx, Dd = _ctx(torch, v.D, torch.float32, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=cfg["eps"],
-                   max_iter=cfg["max_iter"], seed=cfg["index_seed"], resample=True)
-    it, e, rc = ctx.solve()
-    A, B = factors_np(ctx)
-    # the oracle's last iteration from the GPU's previous factors (a full
-    # oracle run at this size takes minutes): one step, same sets
-    ctx2, _ = _ctx(torch, Dd, None, r, sI, sJ, Lmax, gamma=cfg["gamma"], eps=-1.0, max_iter=it,
-                   seed=cfg["index_seed"], resample=True)
-    ctx2.enqueue(it - 1)
-    ctx2.sync()
-    Ap, Bp = factors_np(ctx2)
-    ctx2.close()
-    I, J = sampler.draw_IJ(cfg["index_seed"], it - 1, v.D.shape[0], v.D.shape[1], sI, sJ)
-    D64 = v.D.astype(np.float64)
-    ref = O.step(D64, Ap, Bp, I, J, Lmax * cfg["gamma"] ** (it - 1), r)
-    d = O.factored_rel_diff(A, B, ref["A1"], ref["B1"])
-    truth = O.factored_rel_diff(A, B, v.F, v.G.T)
-    print("iters", it, "e", e, "last step vs oracle", d, "vs background", truth, flush=True)
-    assert e <= 1e-5
-    assert d <= 1e-5
-    # sampled entries of L against the oracle's product
-    rng = np.random.default_rng(0)
-    ii = rng.integers(0, v.D.shape[0], 2000)
-    jj = rng.integers(0, v.D.shape[1], 2000)
-    Lg = np.einsum("ij,ji->i", A[ii, :], B[:, jj])
-    Lo = np.einsum("ij,ji->i", ref["A1"][ii, :], ref["B1"][:, jj])
-    assert np.max(np.abs(Lg - Lo)) <= 1e-4 * np.abs(Lo).max()
     ctx.close()
 
 

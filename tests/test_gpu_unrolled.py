@@ -89,9 +89,10 @@ def test_backward_matches_oracle_f64():
     dz = ub.backward().cpu().numpy()
     flags = ub.status()
     _, ref, _ = _oracle(items, r, zetas, tau)
-    err = np.abs(dz - ref).max() / np.abs(ref).max()
-    print("dzeta", dz, ref, "err", err, "flags", flags, flush=True)
-    assert err <= 1e-9
+    err = np.abs(dz - ref) / np.abs(ref)
+    print("dzeta", dz, ref, "per-component rel err", err, "flags", flags, flush=True)
+    # every component on its own scale (d zeta_k spans several decades)
+    assert np.all(np.abs(dz - ref) <= 1e-9 * np.abs(ref) + 1e-14 * np.abs(ref).max())
     assert not np.any(flags & 1)
     ub.close()
 
@@ -118,6 +119,7 @@ def test_G2_central_differences_on_device():
     ub.forward(torch.tensor(zetas))
     dz = ub.backward().cpu().numpy()
     fd = np.zeros(K)
+    floor = np.zeros(K)
     for k in range(K):
         h = 1e-5 * zetas[k]
         zp, zm = zetas.copy(), zetas.copy()
@@ -126,9 +128,13 @@ def test_G2_central_differences_on_device():
         lp = float(ub.forward(torch.tensor(zp)).sum())
         lm = float(ub.forward(torch.tensor(zm)).sum())
         fd[k] = (lp - lm) / (zp[k] - zm[k])
-    err = np.abs(fd - dz).max() / np.abs(dz).max()
-    print("fd", fd, "adjoint", dz, "err", err, flush=True)
-    assert err <= 1e-6
+        # round-off of the difference quotient: a few ulps of the loss over 2h
+        # (the forward's SVDs stop at 1e-13 relative, which sets the ulp count)
+        floor[k] = 1e3 * 2.0 ** -52 * (abs(lp) + abs(lm)) / (zp[k] - zm[k])
+    err = np.abs(fd - dz) / np.abs(dz)
+    print("fd", fd, "adjoint", dz, "per-component rel err", err, "floor", floor, flush=True)
+    # each component on its own scale: |fd_k - dz_k| <= 1e-6 |dz_k| + round-off floor
+    assert np.all(np.abs(fd - dz) <= 1e-6 * np.abs(dz) + floor)
     ub.close()
 
 
@@ -143,10 +149,38 @@ def test_f32_against_f64_oracle():
     dz = ub.backward().cpu().numpy()
     ref_l, ref_g, _ = _oracle(items, r, zetas, tau, f32=True)
     lerr = np.abs(loss - ref_l).max() / np.abs(ref_l).max()
-    gerr = np.abs(dz - ref_g).max() / np.abs(ref_g).max()
-    print("f32 loss err", lerr, "grad err", gerr, flush=True)
-    assert lerr <= 1e-4 and gerr <= 1e-4
+    gerr = np.abs(dz - ref_g) / np.abs(ref_g)
+    print("f32 loss err", lerr, "grad per-component rel err", gerr, flush=True)
+    assert lerr <= 1e-4
+    assert np.all(np.abs(dz - ref_g) <= 1e-4 * np.abs(ref_g) + 1e-6 * np.abs(ref_g).max())
     ub.close()
+
+
+def test_f32_full_batch_against_f64_oracle():
+    """The unrolled workload as the benchmark runs it: 32 planted instances,
+    n ~ U{1000..3000}, alpha ~ U[0.1, 0.3], r = 5, |I| = |J| = ceil(20 ln n),
+    K = 10, tau_rel = 0.05, FP32 data and factors; every instance's loss and
+    the batch's d loss / d zeta against the FP64 oracle on the float-rounded
+    data."""
+    torch = require_gpu()
+    batch = synth.unrolled_batch(nb=32, r=5, seed=7)
+    r, K, tau = 5, 10, 0.05
+    zetas = 0.7 ** np.arange(K) * float(np.mean([it.inst.Lmax for it in batch]))
+    items = [(it.inst, it.s, 1000 + b) for b, it in enumerate(batch)]
+    print("case unrolled f32 full batch (32 instances)", flush=True)
+    ub = _gpu_batch(torch, items, r, K, tau, torch.float32)
+    loss = ub.forward(torch.tensor(zetas)).cpu().numpy()
+    dz = ub.backward().cpu().numpy()
+    flags = ub.status()
+    ub.close()
+    ref_l, ref_g, _ = _oracle(items, r, zetas, tau, f32=True)
+    lerr = np.abs(loss - ref_l) / np.abs(ref_l)
+    gerr = np.abs(dz - ref_g) / np.abs(ref_g)
+    print("loss per-instance rel err max", lerr.max(), "grad per-component rel err", gerr, "flags",
+          np.bitwise_or.reduce(flags), flush=True)
+    assert lerr.max() <= 1e-4
+    assert np.all(np.abs(dz - ref_g) <= 1e-4 * np.abs(ref_g) + 1e-6 * np.abs(ref_g).max())
+    assert not np.any(flags & 16)
 
 
 def test_autograd_function():

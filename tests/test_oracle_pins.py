@@ -268,3 +268,81 @@ def test_rank_deficient_core_drops_components():
     out = O.step(D, np.zeros((100, 4)), np.zeros((4, 90)), I, J, np.inf, 4)
     assert out["keep"].tolist() == [True, True, False, False]
     assert np.linalg.norm(out["A1"] @ out["B1"] - D) <= 1e-12 * np.linalg.norm(D)
+
+
+# ------------------------------- the factored difference metric ----------
+
+def _dense_rel(A1, B1, A0, B0):
+    L1, L0 = A1 @ B1, A0 @ B0
+    return np.linalg.norm(L1 - L0) / np.linalg.norm(L0)
+
+
+@pytest.mark.parametrize("n1,n2,r1,r0", [(40, 30, 3, 3), (25, 60, 2, 5), (70, 20, 6, 1), (12, 12, 12, 12)])
+def test_factored_rel_diff_equals_dense_norm(n1, n2, r1, r0):
+    """||A1 B1 - A0 B0||_F / ||A0 B0||_F from thin QRs equals the norm of the
+    formed difference (generic factors of unequal ranks)."""
+    rng = np.random.default_rng(n1 * 131 + n2 * 7 + r1 + r0)
+    A0, B0 = rng.standard_normal((n1, r0)), rng.standard_normal((r0, n2))
+    A1, B1 = rng.standard_normal((n1, r1)), rng.standard_normal((r1, n2))
+    want = _dense_rel(A1, B1, A0, B0)
+    assert abs(O.factored_rel_diff(A1, B1, A0, B0) - want) <= 1e-13 * want
+    # a small perturbation (the regime of every parity assertion)
+    A2 = A0 + 1e-9 * rng.standard_normal(A0.shape)
+    want = _dense_rel(A2, B0, A0, B0)
+    assert abs(O.factored_rel_diff(A2, B0, A0, B0) - want) <= 1e-6 * want
+
+
+def test_factored_rel_diff_closed_forms():
+    """Values fixed by the definition: the same product in another basis gives
+    0, the negated product 2, a doubled product 1, and the metric is not
+    symmetric in its two pairs (the denominator is the second product)."""
+    rng = np.random.default_rng(5)
+    A0, B0 = rng.standard_normal((50, 4)), rng.standard_normal((4, 45))
+    T = rng.standard_normal((4, 4)) + 4 * np.eye(4)
+    assert O.factored_rel_diff(A0 @ T, np.linalg.solve(T, B0), A0, B0) <= 1e-13
+    assert abs(O.factored_rel_diff(-A0, B0, A0, B0) - 2.0) <= 1e-13
+    assert abs(O.factored_rel_diff(2 * A0, B0, A0, B0) - 1.0) <= 1e-13
+    assert abs(O.factored_rel_diff(A0, B0, 2 * A0, B0) - 0.5) <= 1e-13
+    # a difference confined to one entry of the product
+    A1 = np.hstack([A0, np.zeros((50, 1))]); A1[7, 4] = 1.0
+    B1 = np.vstack([B0, np.zeros((1, 45))]); B1[4, 11] = 3.0
+    want = 3.0 / np.linalg.norm(A0 @ B0)
+    assert abs(O.factored_rel_diff(A1, B1, A0, B0) - want) <= 1e-13 * want
+
+
+# ------------------------------------------------- the pinv rule ---------
+
+@pytest.mark.parametrize("spectrum", [[1.0, 1e-2, 1e-4, 1e-6], [1.0, 1e-8, 1e-12, 1e-16],
+                                      [3.0, 3.0 * 2e-14, 3.0 * 1e-14, 3.0 * 1e-17]])
+def test_pinv_rule_on_graded_spectra(spectrum):
+    """U^+ of H_r(M), Moore-Penrose with the cut at max(|I|,|J|) 2^-52 sigma_1,
+    on cores with planted singular vectors and graded singular values (the
+    last case straddles the cut: for a 40 x 36 core it is 8.9e-15 relative).
+    The kept set is exactly the planted values above the cut, and U^+ equals
+    the closed form V_k diag(1/sigma_k) W_k^T of the planted factors within
+    the backward-stable bound of an SVD, ~ max(m, n) eps sigma_1 / sigma_min
+    (relative), with sigma_min the smallest kept value."""
+    rng = np.random.default_rng(7)
+    m, n, r = 40, 36, len(spectrum)
+    Wq, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.zeros(min(m, n))
+    s[:r] = spectrum
+    s[r:] = spectrum[-1] * 1e-3 * np.linspace(1.0, 0.5, s.size - r)
+    M = (Wq[:, :s.size] * s) @ Vq[:, :s.size].T
+    Wr, sr, Vr, keep = O.truncated_svd_pinv(M, r)
+    cut = max(m, n) * 2.0 ** -52 * spectrum[0]
+    assert keep.tolist() == [v > cut for v in spectrum]
+    inv = np.where(keep, 1.0 / np.where(keep, sr, 1.0), 0.0)
+    Up = (Vr * inv) @ Wr.T
+    k = np.array(keep)
+    exact = (Vq[:, :r][:, k] / np.array(spectrum)[k]) @ Wq[:, :r][:, k].T
+    smin = min(v for v in spectrum if v > cut)
+    bound = 10.0 * max(m, n) * 2.0 ** -52 * spectrum[0] / smin
+    assert np.linalg.norm(Up - exact) <= max(bound, 1e-13) * np.linalg.norm(exact)
+    # and the library's pinv of the formed H_r agrees on the well-graded case
+    if spectrum[-1] / spectrum[0] >= 1e-6:
+        Uw, Us, Uvt = np.linalg.svd(M)
+        Hr = (Uw[:, :r] * Us[:r]) @ Uvt[:r, :]
+        want = np.linalg.pinv(Hr, rcond=max(m, n) * 2.0 ** -52)
+        assert np.linalg.norm(Up - want) <= 1e-8 * np.linalg.norm(want)
