@@ -195,6 +195,22 @@ int ircur_get_cur(ircur_ctx* ctx, void* C_dev, void* Upinv_dev, void* R_dev,
 int ircur_to_svd(ircur_ctx* ctx, double* W_dev, double* sigma_dev, double* V_dev);
 
 /*
+ * ircur_to_svd for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same outputs, bit for bit, but the workspace
+ * (Gram partials and the small maps) is a fixed array inside the library,
+ * one per device, 4.03 MiB (enough for r <= IRCUR_MAX_RANK and any n1, n2),
+ * set up by ircur_init; nothing is allocated or freed.  Calls on one device
+ * share that array: calls that overlap on one device (other host threads,
+ * other streams) race and must be serialised by the caller.  Every entry of
+ * the workspace a call reads is written earlier in the same call, so nothing
+ * carries over between calls.  IRCUR_ERR_UNSUPPORTED if the workspace would
+ * exceed the array, IRCUR_ERR_STATE if ircur_init could not set it up on the
+ * context's device.  Synchronises.
+ */
+int ircur_to_svd_noalloc(ircur_ctx* ctx, double* W_dev, double* sigma_dev, double* V_dev);
+
+/*
  * Full sparse part S = T_zeta(D - A_k B_k) over all of D (the hard threshold
  * of eq. (4) applied to every entry; the foreground of the video application
  * of section 4.2), written to S_dev (n1 x n2, row stride ldS >= n2, dtype of D,

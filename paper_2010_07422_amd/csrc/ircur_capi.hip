@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -81,6 +82,56 @@ float round_down_float(double z) {
     if ((double)f > z) f = std::nextafter(f, -INFINITY);
     return f;
 }
+
+}  // namespace
+
+// ------------------------------------------------ fixed device workspace ---
+// The workspace of ircur_to_svd_noalloc, for callers that cannot allocate:
+// Algorithm 2's Gram partials (2 sides x at most 256 workgroups x R x R) and
+// its two pairs of R x R maps, R <= IRCUR_MAX_RANK: 528384 doubles, 4.03 MiB.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` only stands for the symbol: its device address is
+// taken once per device with hipGetSymbolAddress (at ircur_init, with that
+// device current) and only that address is handed to kernels.
+namespace {
+constexpr size_t kScratchDoubles = 2 * 256 * (size_t)IRCUR_MAX_RANK * IRCUR_MAX_RANK
+                                   + 4 * (size_t)IRCUR_MAX_RANK * IRCUR_MAX_RANK;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// Looks up (once per device; the device must be current) and returns the
+// device address of `scratch`; nullptr when the lookup fails.
+double* noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_dev[device] = (double*)ptr;
+    }
+    return g_scratch_dev[device];
+}
+
+double* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
+// Workgroups per side of Algorithm 2's Gram kernel and the workspace it needs.
+int alg2_groups(const ircur_params& p) {
+    return (int)std::min<int64_t>(256, (std::max(p.n1, p.n2) + 127) / 128);
+}
+size_t alg2_doubles(int nwg, size_t R) { return 2 * (size_t)nwg * R * R + 4 * R * R; }
 
 }  // namespace
 
@@ -530,6 +581,7 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->svd_lds = lds;
     c->stream = (hipStream_t)stream;
     (void)hipGetDevice(&c->device);
+    if (!noalloc_setup(c->device)) { delete c; return IRCUR_ERR_DEVICE; }
     c->esz = p.dtype == IRCUR_F64 ? 8 : (p.dtype == IRCUR_F32 ? 4 : 2);
     c->fsz = p.dtype == IRCUR_F64 ? 8 : 4;
     c->D = D_dev;
@@ -828,30 +880,49 @@ int ircur_get_cur(ircur_ctx* c, void* C_dev, void* Upinv_dev, void* R_dev, void*
     return IRCUR_OK;
 }
 
-int ircur_to_svd(ircur_ctx* c, double* W_dev, double* sigma_dev, double* V_dev) {
-    if (!c) return IRCUR_ERR_ARG;
-    int rc = read_state(c);
-    if (rc) return rc;
+// Algorithm 2 on the current factors with the workspace ws: the Gram
+// partials (2 x nwg x R x R doubles, every entry rewritten by the launch),
+// then T1 and Tf (2 x R x R each, rewritten as well).
+static int to_svd_with(ircur_ctx* c, double* ws, double* W_dev, double* sigma_dev, double* V_dev) {
     const ircur_params& p = c->p;
-    const int nwg = (int)std::min<int64_t>(256, (std::max(p.n1, p.n2) + 127) / 128);
+    const int nwg = alg2_groups(p);
     const size_t R = c->R;
-    if (!c->alg2_buf) {
-        // parts (2 x 256 x R x R), T1 and Tf (2 x R x R each)
-        TRY_ALLOC(c, dalloc(c, &c->alg2_buf, 2 * 256 * R * R + 4 * R * R));
-    }
     Alg2Args a{};
     const int cur = c->k & 1;
     a.X[0] = c->At[cur]; a.X[1] = c->B[cur];
     a.n[0] = p.n1; a.n[1] = p.n2;
     a.r = p.r; a.R = c->R; a.fdt = p.dtype == IRCUR_F64 ? 0 : 1; a.nwg = nwg;
-    a.parts = c->alg2_buf;
-    a.T1 = c->alg2_buf + 2 * 256 * R * R;
+    a.parts = ws;
+    a.T1 = ws + 2 * (size_t)nwg * R * R;
     a.Tf = a.T1 + 2 * R * R;
     a.sigma_out = sigma_dev;
     a.out[0] = W_dev; a.out[1] = V_dev;
     HIPCHK(c, launch_alg2(a, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return IRCUR_OK;
+}
+
+int ircur_to_svd(ircur_ctx* c, double* W_dev, double* sigma_dev, double* V_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    if (!c->alg2_buf) {
+        const size_t R = c->R;
+        TRY_ALLOC(c, dalloc(c, &c->alg2_buf, alg2_doubles(alg2_groups(c->p), R)));
+    }
+    return to_svd_with(c, c->alg2_buf, W_dev, sigma_dev, V_dev);
+}
+
+int ircur_to_svd_noalloc(ircur_ctx* c, double* W_dev, double* sigma_dev, double* V_dev) {
+    if (!c) return IRCUR_ERR_ARG;
+    double* ws = noalloc_scratch(c->device);
+    if (!ws) return fail(c, IRCUR_ERR_STATE, "no-allocation workspace not set up on this device");
+    const size_t need = alg2_doubles(alg2_groups(c->p), (size_t)c->R);
+    if (need > kScratchDoubles)
+        return fail(c, IRCUR_ERR_UNSUPPORTED, "Algorithm 2 workspace exceeds the fixed no-allocation array");
+    int rc = read_state(c);
+    if (rc) return rc;
+    return to_svd_with(c, ws, W_dev, sigma_dev, V_dev);
 }
 
 static SparseArgs sparse_args(const ircur_ctx* c, double zeta, void* S_dev, int64_t ldS) {

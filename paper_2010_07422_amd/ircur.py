@@ -67,6 +67,7 @@ _SIGS = {
     "ircur_get_core": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "ircur_get_cur": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "ircur_to_svd": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ircur_to_svd_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "ircur_sparse_full": (ctypes.c_int, [_P, ctypes.c_double, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "ircur_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "ircur_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
@@ -289,18 +290,23 @@ class IRCUR:
         out["I"], out["J"] = self.sets()
         return out
 
-    def to_svd(self):
+    def to_svd(self, out=None, noalloc=False):
         """Algorithm 2 on the current factors: (W n1 x r, sigma r, V n2 x r),
-        float64, L_k = W diag(sigma) V^T."""
+        float64, L_k = W diag(sigma) V^T.  out: optional (W, sigma, V)
+        tensors to fill; noalloc selects ircur_to_svd_noalloc."""
         import torch
         n1, n2, r = self.p.n1, self.p.n2, self.p.r
         dev = self.D.device
-        W = torch.empty((n1, r), dtype=torch.float64, device=dev)
-        sig = torch.empty((r,), dtype=torch.float64, device=dev)
-        V = torch.empty((n2, r), dtype=torch.float64, device=dev)
-        self._check(lib().ircur_to_svd(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in (W, sig, V))),
-                    "ircur_to_svd")
-        return W, sig, V
+        if out is None:
+            out = (torch.empty((n1, r), dtype=torch.float64, device=dev),
+                   torch.empty((r,), dtype=torch.float64, device=dev),
+                   torch.empty((n2, r), dtype=torch.float64, device=dev))
+        for t, shape in zip(out, ((n1, r), (r,), (n2, r))):
+            if t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous() or t.device != dev:
+                raise ValueError("out must hold contiguous float64 tensors of shapes (n1, r), (r,), (n2, r)")
+        name = "ircur_to_svd_noalloc" if noalloc else "ircur_to_svd"
+        self._check(getattr(lib(), name)(self.h, *(ctypes.c_void_p(t.data_ptr()) for t in out)), name)
+        return out
 
     def sparse_full(self, zeta=-1.0, out=None):
         """T_zeta(D - A_k B_k) over all of D in the dtype of D; zeta < 0 picks
