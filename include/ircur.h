@@ -301,6 +301,9 @@ int ircur_sample(uint64_t seed, int64_t t, int64_t n1, int64_t n2, int32_t sI,
  * otherwise).  Synchronises.
  */
 int ircur_get_phase_profile(ircur_ctx* ctx, double* us16);
+/* Profile builds: the same timers for a second launch of the one-launch SVD
+ * issued straight after the first with the same inputs (zeros otherwise). */
+int ircur_get_phase_profile2(ircur_ctx* ctx, double* us16);
 
 void        ircur_destroy(ircur_ctx* ctx);
 const char* ircur_strerror(int status);

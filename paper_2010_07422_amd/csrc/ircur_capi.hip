@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -174,6 +175,10 @@ struct ircur_ctx {
     double* Zr = nullptr;           // reduced Z of the SVD (sJ16 x 16)
     double* rp = nullptr;           // SVD residual parts (G)
     bool lds_svd = false;           // the SVD keeps its block of M in LDS (P = 16)
+    bool csvd = false;              // core gather and SVD in one launch (ircur_csvd.hip)
+    int Gc = 0;                     // its workgroups, ceil(sI / 16)
+    size_t csvd_lds = 0;
+    double* Xr = nullptr;           // its exchange block (sJ16 x 16)
     int32_t* Icur = nullptr;        // index sets of an export (device)
     int32_t* Jcur = nullptr;
     unsigned long long* nnz = nullptr;
@@ -282,7 +287,7 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
-                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
+                    c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Xr, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
                     c->info, c->hist};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -396,6 +401,44 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     hipStream_t s = c->stream;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][0], s));
 
+    bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
+                 std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
+    if (c->csvd) {
+        CoreArgs ca{};
+        ca.D = c->D; ca.ldD = p.ldD; ca.I = Id; ca.J = Jd; ca.sI = p.sI; ca.sJ = p.sJ;
+        ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
+        ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.MA = c->MA; ca.MB = nullptr; ca.st = c->st;
+        ca.Abc = c->Abc; ca.Bsc = c->Bsc;
+        HIPCHK(c, launch_core(ca, p.dtype, c->R, s));
+        CsvdArgs ka{};
+        ka.D = c->D; ka.ldD = p.ldD; ka.I = Id; ka.J = Jd; ka.sI = p.sI; ka.sJ = p.sJ;
+        ka.r = p.r; ka.R = c->R; ka.n1 = p.n1; ka.n2 = p.n2;
+        ka.At = c->At[cur]; ka.B = c->B[cur];
+        ka.MA = c->MA; ka.Abc = c->Abc; ka.Bsc = c->Bsc;
+        ka.G = c->Gc;
+        ka.max_it = p.svd_max_it > 0 ? p.svd_max_it : 256;
+        ka.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : (p.dtype == IRCUR_F32 ? 1e-9 : 1e-7));
+        ka.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
+        ka.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
+        ka.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
+        ka.prevV = c->prevV; ka.Zp = c->Zp; ka.Gp = c->Gp; ka.Xr = c->Xr; ka.rp = c->rp;
+        ka.W = c->W; ka.V = c->V; ka.sigma = c->sigma;
+        ka.rowI = c->rowI; ka.rowJ = c->rowJ; ka.qs = row_stride(c->R, (int)c->fsz);
+        ka.GmI = c->GmI; ka.GmJ = c->GmJ; ka.scaleJ = c->scaleJ; ka.TAd = c->TAd;
+        ka.info = c->info + k; ka.st = c->st;
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][1], s));
+        HIPCHK(c, launch_csvd(ka, p.dtype, c->csvd_lds, s));
+#ifdef IRCUR_PHASE_PROFILE
+        // profile builds: the same launch again, straight after (same inputs,
+        // same outputs for a warm start other than the previous basis), timed
+        // into the second set of phase timers
+        if (ka.warm != 1 && std::getenv("IRCUR_PROFILE_REPEAT")) {
+            ka.prof_slot = 1;
+            HIPCHK(c, launch_csvd(ka, p.dtype, c->csvd_lds, s));
+        }
+#endif
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
+    } else {
     CoreArgs ca{};
     ca.D = c->D; ca.ldD = p.ldD; ca.I = Id; ca.J = Jd; ca.sI = p.sI; ca.sJ = p.sJ;
     ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
@@ -415,8 +458,6 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     // residual, max(1e-7, 1e-2 e_k) (an SVD a hundred times finer than the
     // iterate it updates; the last iterations get 1e-7)
     sa.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
-    bool sameJ = c->have_prevV && (int)c->lastJ.size() == p.sJ &&
-                 std::equal(c->lastJ.begin(), c->lastJ.end(), Jhost);
     sa.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
     sa.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
     sa.prevV = c->prevV; sa.prevV_out = c->prevV;
@@ -435,9 +476,10 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     } else {
         HIPCHK(c, launch_svd(sa, p.dtype, c->svd_lds, s));
     }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
+    }
     c->have_prevV = true;
     c->lastJ.assign(Jhost, Jhost + p.sJ);
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][2], s));
 
     const PassArgs pa = pass_args(c, k, Id, Jd);
     HIPCHK(c, launch_pass(pa, p.dtype, c->R, s));
@@ -579,6 +621,20 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     }
     c->psvd = pb;
     c->svd_lds = lds;
+    {
+        // one launch for the core and the SVD: R <= 16, one workgroup per 16
+        // rows of M, all co-resident (at most one per compute unit), LDS fit
+        int ncu = 0;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+        const int gc = (p.sI + 15) / 16;
+        if (c->R <= 16 && gc <= ncu && p.sJ <= 512 && csvd_lds_bytes(p.sJ, gc) <= 160 * 1024) {
+            c->csvd = true;
+            c->Gc = gc;
+            c->csvd_lds = csvd_lds_bytes(p.sJ, gc);
+        }
+    }
     c->stream = (hipStream_t)stream;
     (void)hipGetDevice(&c->device);
     if (!noalloc_setup(c->device)) { delete c; return IRCUR_ERR_DEVICE; }
@@ -631,7 +687,7 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     {
         const size_t sI16 = ((size_t)p.sI + 15) / 16 * 16, sJ16 = ((size_t)p.sJ + 15) / 16 * 16;
         TRY(dalloc(c, &c->Zp, (size_t)c->G * sJ16 * c->psvd));
-        if (c->lds_svd) {
+        if (c->lds_svd || c->csvd) {
             TRY(dalloc(c, &c->Abc, sI16 * 16));
             TRY(dalloc(c, &c->Bsc, 16 * sJ16));
             TRY(dalloc(c, &c->Zr, sJ16 * 16));
@@ -642,6 +698,20 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     }
     TRY(dalloc(c, &c->Gp, (size_t)c->G * 2 * c->psvd * c->psvd));
     TRY(dalloc(c, &c->prevV, (size_t)p.sJ * R));
+    if (c->csvd) {
+        const size_t sJ16 = ((size_t)p.sJ + 15) / 16 * 16;
+        // the one-launch SVD's partials, exchange block and basis of the last launch
+        (void)hipFree(c->Zp); c->Zp = nullptr;
+        (void)hipFree(c->Gp); c->Gp = nullptr;
+        (void)hipFree(c->prevV); c->prevV = nullptr;
+        TRY(dalloc(c, &c->Zp, (size_t)c->Gc * sJ16 * 16));
+        TRY(dalloc(c, &c->Gp, (size_t)c->Gc * 768));
+        TRY(dalloc(c, &c->prevV, sJ16 * 16));
+        TRY(dalloc(c, &c->Xr, sJ16 * 16));
+        if (!c->rp) TRY(dalloc(c, &c->rp, (size_t)c->Gc));
+        else { (void)hipFree(c->rp); c->rp = nullptr; TRY(dalloc(c, &c->rp, (size_t)c->Gc)); }
+        HIPCHK(c, hipMemset(c->Xr, 0, sJ16 * 16 * sizeof(double)));
+    }
     TRY(dalloc(c, &c->W, (size_t)p.sI * R));
     TRY(dalloc(c, &c->V, (size_t)p.sJ * R));
     TRY(dalloc(c, &c->sigma, R * R));
@@ -1121,6 +1191,14 @@ int ircur_get_phase_profile(ircur_ctx* c, double* us16) {
     int rc = read_state(c);
     if (rc) return rc;
     for (int i = 0; i < 16; ++i) us16[i] = (double)c->st_host->phase[i] * 0.01;   // 100 MHz ticks
+    return IRCUR_OK;
+}
+
+int ircur_get_phase_profile2(ircur_ctx* c, double* us16) {
+    if (!c || !us16) return IRCUR_ERR_ARG;
+    int rc = read_state(c);
+    if (rc) return rc;
+    for (int i = 0; i < 16; ++i) us16[i] = (double)c->st_host->phase2[i] * 0.01;
     return IRCUR_OK;
 }
 

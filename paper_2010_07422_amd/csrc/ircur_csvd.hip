@@ -1,0 +1,807 @@
+// Phase I on the sampled block and Phase II of Algorithm 1 in one launch
+// (FP64 subspace arithmetic, ranks r <= 16):
+//
+//   core    M = [D - S_{k+1}]_{I,J}, S_{k+1} = T_zeta[D - L_k] on the block
+//           (eq. (4), (5)), gathered straight into LDS: workgroup g owns the
+//           16 rows I_{16g .. 16g+15} of M;
+//   svd     an orthonormal basis Q (|J| x 16) whose first r columns span the
+//           top-r right singular subspace of M (section 3.1), by subspace
+//           iteration on A = M^T M accelerated with Chebyshev filters;
+//   output  the per-row data and small maps of the fused pass, in the
+//           basis-free form U^+ = Q_r (Y^T Y)^-1 Y^T, Y = M Q_r (see
+//           ircur_svd.hip for the identities).
+//
+// Subspace iteration.  The block X has 16 columns; the first r are the
+// wanted subspace (Cholesky QR keeps the span of the leading columns, so the
+// others never perturb it) and the remaining ones, pushed towards the next
+// singular directions by the same filters, give Rayleigh quotients below
+// sigma_{r+1}^2 that set the filter interval and the gap estimate.  Work
+// proceeds in sweeps:
+//   test    with X = Q orthonormal: Z = A Q, Gy = Q^T A Q; converged when
+//           ||Z_r - Q_r Gy_rr||_F <= tol ||Gy_rr||_F (first r columns);
+//   filter  otherwise m applications of the scaled three-term Chebyshev
+//           recurrence (Zhou and Saad 2007) for the interval [0, b], b the
+//           largest Rayleigh quotient of the extra columns, normalised at the
+//           largest quotient of the wanted ones, then Cholesky QR;
+// the test application is also the first filter step.  With b = 0 (no
+// extra columns, or before the columns have separated) a step is a scaled
+// power step, i.e. plain subspace iteration.
+//
+// One application of A: each workgroup forms Y_blk = M_blk X (16 x 16) and
+// its partial Z_g = M_blk^T Y_blk (|J| x 16) on the matrix cores, publishes
+// the partial, and after a grid barrier reduces its slice of row tiles of Z
+// (and, on a test, the small Grams) in a fixed order, forms its slice of the
+// next X, publishes it, and after a second barrier reads the whole next X.
+// Data exchanged between workgroups uses device-scope stores and loads, so
+// the barriers need no cache-wide fence.  Every workgroup holds the reduced
+// small matrices and takes identical decisions.
+#include "ircur_small.h"
+#include "ircur_device.h"
+
+#include <stdint.h>
+
+namespace ircur {
+
+namespace {
+
+constexpr int P = 16;
+
+template <typename T> struct FactorOf;
+template <> struct FactorOf<double> { typedef double type; };
+template <> struct FactorOf<float> { typedef float type; };
+template <> struct FactorOf<bf16_t> { typedef float type; };
+
+__device__ __forceinline__ void st_dev(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier over the G workgroups (all resident: G is at most the number
+// of compute units and each workgroup takes one).  Every thread's stores have
+// completed before its workgroup is counted; the spin is bounded (a flag is
+// raised on time-out and the kernel runs on, so every wave reaches its end).
+__device__ void grid_sync(uint32_t* ctr, uint32_t target, int32_t* fail) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > (1u << 22)) {
+                __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+// Sum over the G partials of one 256-double block (block index `blk` of each
+// partial, partials `pstride` doubles apart), thread t summing entry t in
+// partial order; loads issued 16 at a time.
+__device__ __forceinline__ double sum_parts(const double* base, size_t pstride, int G) {
+    double s = 0.0;
+    for (int g0 = 0; g0 < G; g0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = g0 + u < G ? ld_dev(base + (size_t)(g0 + u) * pstride) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    return s;
+}
+
+}  // namespace
+
+// Phase timers of profile builds: 100 MHz ticks accumulated in registers of
+// the first thread and written once at the end of the launch.
+#ifdef IRCUR_PHASE_PROFILE
+#define CPHASE(i)                                                             \
+    do {                                                                      \
+        const uint64_t t_ = __builtin_amdgcn_s_memrealtime();                 \
+        ph_[i] += t_ - t_prev;                                                \
+        t_prev = t_;                                                          \
+    } while (0)
+#else
+#define CPHASE(i) do { } while (0)
+#endif
+
+struct QTimes { uint64_t g, c, x; };
+
+// M block in LDS: k-step ks (4 columns of M) holds its 4 x 16 entries with a
+// column stride of 17 doubles, so that both the row-tiled reads of M X and
+// the column-tiled reads of M^T Y fall on distinct banks.
+__device__ __forceinline__ int mb_index(int row, int col) { return (col >> 2) * 68 + (col & 3) * 17 + row; }
+
+// The block X (|J| x 16) in LDS with a row stride of 17 doubles (the reads of
+// a 16-row tile by rows and by columns both avoid bank conflicts).
+constexpr int XS = 17;
+
+namespace {
+
+// G = X^T X over the first 4 KS rows of X: k-steps split over the four
+// waves, each with two accumulator chains; partial tiles summed in order.
+__device__ __forceinline__ void gram16(const double* X, int KS, double* scr, double* G) {
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int per = (KS + 3) >> 2;
+    const int k0 = min(KS, w * per), k1 = min(KS, (w + 1) * per);
+    d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+    for (int ks = k0; ks < k1; ks += 2) {
+        const bool two = ks + 1 < k1;
+        const double x1 = X[(4 * ks + (l >> 4)) * XS + (l & 15)];
+        const double x2 = two ? X[(4 * (ks + 1) + (l >> 4)) * XS + (l & 15)] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, x2, acc2, 0, 0, 0);
+    }
+    acc += acc2;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) scr[w * 256 + ((l >> 4) + 4 * v) * 16 + (l & 15)] = acc[v];
+    __syncthreads();
+    G[tid] = ((scr[tid] + scr[256 + tid]) + scr[512 + tid]) + scr[768 + tid];
+    __syncthreads();
+}
+
+// X <- X T for the row tiles of X (T 16 x 16 row-major in LDS), in place:
+// each tile's rows are read before they are written.
+__device__ __forceinline__ void xmul16(double* X, int ntiles, const double* T) {
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    for (int t = w; t < ntiles; t += 4) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        double av[4], bv[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            av[ks] = X[(16 * t + (l & 15)) * XS + 4 * ks + (l >> 4)];
+            bv[ks] = T[(4 * ks + (l >> 4)) * 16 + (l & 15)];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[(16 * t + (l >> 4) + 4 * v) * XS + (l & 15)] = acc[v];
+    }
+    __syncthreads();
+}
+
+// Cholesky QR of the first `live` columns of X (rows >= rows_valid zero):
+// X <- X L^-T with X^T X = L L^T, on the column-equilibrated Gram matrix
+// (columns scaled to unit norm first: a column that is merely small after a
+// power step is not mistaken for a dependent one).  A second pass runs when the first pivots
+// spread by more than `kappa2_one` in squared condition (its rounding of
+// X^T X would show in the orthogonality) and whenever a column was found
+// dependent (refilled with pseudo-random entries); at most four passes.
+__device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, int live, double kappa2_one, int min_passes,
+                         double* Gs, double* Ls, double* Li, double* LiT, int* dead, double* scr, uint64_t salt) {
+    const int KS = sJ16 / 4, nt = sJ16 / 16;
+    int need = min_passes;
+    QTimes qt = {0, 0, 0};
+#ifdef IRCUR_PHASE_PROFILE
+    uint64_t t_ = __builtin_amdgcn_s_memrealtime();
+#define QPHASE(f) do { const uint64_t n_ = __builtin_amdgcn_s_memrealtime(); qt.f += n_ - t_; t_ = n_; } while (0)
+#else
+#define QPHASE(f) do { } while (0)
+#endif
+    for (int pass = 0; pass < 4; ++pass) {
+        gram16(X, KS, scr, Gs);
+        // Gs <- D^-1 Gs D^-1, D = diag(column norms)
+        {
+            const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+            const double di = Gs[i * 17], dj = Gs[j * 17];
+            const double si = di > 0.0 ? rsqrt_d(di) : 0.0, sj = dj > 0.0 ? rsqrt_d(dj) : 0.0;
+            const double g = Gs[threadIdx.x] * si * sj;
+            __syncthreads();
+            Gs[threadIdx.x] = g;
+            scr[threadIdx.x] = si;      // row scale of the transform (read below as scr[16 * i])
+            __syncthreads();
+        }
+        QPHASE(g);
+        chol_inv<16>(Gs, Ls, Li, dead, 1e-14, live, LiT);
+        // transform D^-1 L^-T: row k of L^-T scaled by 1 / norm of column k
+        {
+            const int k = threadIdx.x >> 4;
+            LiT[threadIdx.x] *= scr[k * 16];
+            __syncthreads();
+        }
+        QPHASE(c);
+        xmul16(X, nt, LiT);
+        QPHASE(x);
+        int nd = 0;
+        double pmax = 0.0, pmin = 0.0;
+        {
+            double dg[16];
+            int dd[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) { dg[j] = Ls[j * 17]; dd[j] = dead[j]; }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j >= live) continue;
+                nd += dd[j];
+                if (!dd[j]) { pmax = fmax(pmax, dg[j]); pmin = pmin == 0.0 ? dg[j] : fmin(pmin, dg[j]); }
+            }
+        }
+        if (pass == 0 && pmin > 0.0 && (pmax / pmin) * (pmax / pmin) > kappa2_one) need = max(need, 2);
+        if (nd > 0) {
+            need = max(need, pass + 2);
+            for (int e = threadIdx.x; e < rows_valid * 16; e += NT) {
+                const int b = e >> 4, c = e & 15;
+                if (c < live && dead[c]) X[b * XS + c] = rnd_unit(salt ^ (0x5bd1e995ull * (uint64_t)(pass + 1)), (uint64_t)e);
+            }
+            __syncthreads();
+        }
+        if (pass + 1 >= need) break;
+    }
+    return qt;
+}
+
+}  // namespace
+
+size_t csvd_lds_bytes(int sJ, int G) {
+    const size_t sJ16 = ((size_t)sJ + 15) / 16 * 16;
+    const size_t ntj = sJ16 / 16;
+    const size_t tpg = (ntj + G - 1) / G;
+    size_t d = 0;
+    d += 17 * sJ16;                   // M block (padded operand order)
+    d += sJ16 * XS;                   // X
+    d += 3 * tpg * 256;               // X_{j-1} slice, reduced Z slice, B_k[:, J] of the slice
+    d += 2 * 256;                     // Y, A_k[I_blk, :]
+    d += 10 * 256;                    // Gy, H, Gs, Ls, Li, LiT, Gam, Gam2, TA, spare
+    d += 4 * 256;                     // MFMA scratch
+    d += 64;                          // reduction buffer
+    return d * sizeof(double) + 96 * sizeof(int);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
+    typedef typename FactorOf<T>::type F;
+    if (a.st->stop) return;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x, l64 = tid & 63, w4 = tid >> 6;
+    const int wg = blockIdx.x, G = a.G;
+#ifdef IRCUR_PHASE_PROFILE
+    uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
+    const uint64_t c_start = __builtin_amdgcn_s_memtime(), r_start = t_prev;
+    uint64_t ph_[16];
+    int ntest_ = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ph_[i] = 0;
+#define QADD(q) do { ph_[13] += (q).g; ph_[14] += (q).c; ph_[15] += (q).x; } while (0)
+#else
+#define QADD(q) do { (void)(q); } while (0)
+#endif
+    const int sI = a.sI, sJ = a.sJ, r = a.r, R = a.R;
+    const int sJ16 = ((sJ + 15) / 16) * 16;
+    const int KS = sJ16 / 4;             // k-steps of M_blk X
+    const int ntj = sJ16 / 16;           // row tiles of Z
+    const int tpg = (ntj + G - 1) / G;   // Z tiles per workgroup
+    const int t0 = wg * tpg;             // first tile of this workgroup's slice
+    const int ntl = max(0, min(tpg, ntj - t0));   // its tiles
+    const int a0 = wg * 16;
+    const int nb = max(0, min(16, sI - a0));
+    const int live = min(16, sJ);         // columns of the block with a direction to hold
+    const int64_t n1 = a.n1, n2 = a.n2;
+    const int fd = sizeof(F) == 8 ? 0 : 1;
+    // a single Cholesky QR pass keeps X^T X within about 16 eps kappa^2 of I
+    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
+    const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
+    const int min_passes = 1;
+
+    double* Mb = smem;                    // 16 x sJ16 at mb_index(row, col)
+    double* X = Mb + 17 * sJ16;           // sJ16 x 16, row stride XS
+    double* Xp = X + sJ16 * XS;           // tpg x 256: X_{j-1} on the slice
+    double* Zs = Xp + tpg * 256;          // tpg x 256: reduced Z on the slice
+    double* Bsl = Zs + tpg * 256;         // tpg x 256: B_k[c, J_b] at [b_local * 16 + c]
+    double* Y = Bsl + tpg * 256;          // 16 x 16
+    double* Ab = Y + 256;                 // 16 x 16
+    double* Gy = Ab + 256;
+    double* H = Gy + 256;
+    double* Gs = H + 256;
+    double* Ls = Gs + 256;
+    double* Li = Ls + 256;
+    double* LiT = Li + 256;
+    double* Gam = LiT + 256;
+    double* Gam2 = Gam + 256;
+    double* TA = Gam2 + 256;
+    double* scr = TA + 512;               // 4 x 256 (one spare block before it)
+    double* red = scr + 4 * 256;          // 64
+    int* dead = (int*)(red + 64);         // 64
+    int* Il = dead + 64;                  // 16
+    int* spare = Il + 16;                 // 16
+    (void)spare;
+
+    // ---- load: the core kernel's M block (row-tiled layout), A_k[I_blk, :], B_k[:, J] ----
+    // (one round trip; the core kernel gathered and thresholded the block on
+    // every compute unit)
+    {
+        const double* __restrict__ src = a.MA + (size_t)wg * KS * 64;   // row tile wg: KS blocks of 64
+        constexpr int UL = 32;            // doubles per thread (|J| <= 512)
+        double mv[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int e = tid + NT * u;
+            mv[u] = e < KS * 64 ? src[e] : 0.0;
+        }
+        const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
+        // B_k[c, J_b] (compact, 16 x sJ16) into X[b][c]
+        double bv[18];
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            const int e = tid + NT * u, c = e / sJ16, b = e - c * sJ16;
+            bv[u] = c < 16 ? a.Bsc[e] : 0.0;
+            (void)b;
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const int e = tid + NT * u;
+            if (e < KS * 64) {
+                const int ks = e >> 6, l = e & 63;
+                Mb[mb_index(l & 15, 4 * ks + (l >> 4))] = mv[u];
+            }
+        }
+        Ab[tid] = (tid >> 4) < nb ? av : 0.0;
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            const int e = tid + NT * u, c = e / sJ16, b = e - c * sJ16;
+            if (c < 16) X[b * XS + c] = bv[u];
+        }
+        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) {      // |J| > 288: the rest
+            const int c = e / sJ16, b = e - c * sJ16;
+            X[b * XS + c] = a.Bsc[e];
+        }
+    }
+    __syncthreads();
+    // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
+    for (int e = tid; e < ntl * 256; e += NT) {
+        const int b = 16 * t0 + (e >> 4), c = e & 15;
+        Bsl[e] = X[b * XS + c];
+    }
+    __syncthreads();
+    // warm start: IRCUR-R keeps B_k[:, J]^T as the wanted columns
+    for (int e = tid; e < sJ16 * 16; e += NT) {
+        const int b = e >> 4, c = e & 15;
+        double v = 0.0;
+        if (b < sJ && c < live) {
+            if (a.warm == 2) v = c < r ? X[b * XS + c] : rnd_unit(a.salt, (uint64_t)e);
+            else v = a.warm == 1 ? a.prevV[e] : rnd_unit(a.salt, (uint64_t)e);
+        }
+        X[b * XS + c] = v;
+    }
+    __syncthreads();
+    CPHASE(0);
+    {
+        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, a.warm == 1 ? 1 : min_passes, Gs, Ls, Li, LiT, dead,
+                                scr, a.salt + 17);
+        QADD(q);
+    }
+    CPHASE(1);
+
+    // ---- subspace iteration -------------------------------------------------
+    double* Zp = a.Zp + (size_t)wg * sJ16 * 16;
+    double* Gp = a.Gp + (size_t)wg * 768;
+    uint32_t nbar = 0;
+    int it = 0;                 // applications of A = M^T M
+    bool test = true;           // this application tests Q (X orthonormal)
+    bool power = true;          // the current sweep uses scaled power steps
+    bool last_power = true;     // ... and the sweep before it
+    double rate = 1.0;          // per-degree residual factor expected of the sweep
+    double spread = 1.0;        // per-degree growth of the largest over the smallest wanted quotient
+    int m = 1, j = 0;           // sweep degree, filter steps done in the sweep
+    double cs = 0.0, es = 0.0, sg1 = 0.0, sg = 0.0, scale = 1.0;
+    double res = 0.0, res_sweep = -1.0;
+    bool conv = false;
+    int plain_next = 0;         // tests whose sweep must use power steps
+    bool no_cheb = false;       // a Chebyshev sweep fell short of its prediction: power steps from here on
+    double bx_prev = -1.0;      // extra columns' largest quotient at the previous test
+    double pred = 1.0;          // residual factor predicted for the current sweep
+    double hi_t = 0.0, lo_t = 0.0;   // largest and smallest wanted quotients at the last test
+    for (;;) {
+        // Y = M_blk X: k-steps split over the four waves, partial tiles summed in order
+        {
+            const int per = (KS + 3) >> 2;
+            const int k0 = min(KS, w4 * per), k1 = min(KS, (w4 + 1) * per);
+            d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+            for (int ks = k0; ks < k1; ks += 4) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = ks + u < k1;
+                    av[u] = in ? Mb[mb_index(l64 & 15, 4 * (ks + u) + (l64 >> 4))] : 0.0;
+                    bv[u] = in ? X[(4 * (ks + u) + (l64 >> 4)) * XS + (l64 & 15)] : 0.0;
+                }
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], acc, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], acc2, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], acc, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], acc2, 0, 0, 0);
+            }
+            acc += acc2;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) scr[w4 * 256 + ((l64 >> 4) + 4 * v) * 16 + (l64 & 15)] = acc[v];
+            __syncthreads();
+            Y[tid] = ((scr[tid] + scr[256 + tid]) + scr[512 + tid]) + scr[768 + tid];
+            __syncthreads();
+        }
+        CPHASE(2);
+        // partial Z_g = M_blk^T Y (tile-lane order); on a test also the partial
+        // Grams Y^T Y, Y^T A_blk and Gamma'_g = B_k[:, J_slice] X_slice
+        for (int tj = w4; tj < ntj; tj += 4) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            const double* mcol = Mb + mb_index(l64 >> 4, 16 * tj + (l64 & 15));
+            double av[4], bv[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                av[ks] = mcol[4 * ks];
+                bv[ks] = Y[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) st_dev(Zp + (size_t)tj * 256 + v * 64 + l64, acc[v]);
+        }
+        if (test && w4 < 3) {
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            if (w4 < 2) {
+                const double* Bop = w4 == 0 ? Y : Ab;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int e = (4 * ks + (l64 >> 4)) * 16 + (l64 & 15);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[e], Bop[e], acc, 0, 0, 0);
+                }
+            } else {
+                for (int q = 0; q < ntl; ++q)
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int bl = 4 * ks + (l64 >> 4);
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Bsl[q * 256 + bl * 16 + (l64 & 15)],
+                                                                   X[(16 * (t0 + q) + bl) * XS + (l64 & 15)], acc, 0, 0, 0);
+                    }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) st_dev(Gp + w4 * 256 + v * 64 + l64, acc[v]);
+        }
+        CPHASE(3);
+        ++nbar;
+        grid_sync(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        CPHASE(4);
+        // reduce: Gy (test) in full, this workgroup's row tiles of Z
+        if (test) Gy[((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15)] = sum_parts(a.Gp + tid, 768, G);
+        for (int q = 0; q < ntl; ++q)
+            Zs[q * 256 + ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15)] =
+                sum_parts(a.Zp + (size_t)(t0 + q) * 256 + tid, (size_t)sJ16 * 16, G);
+        __syncthreads();
+        CPHASE(5);
+        if (test) {
+            // filter of the sweep from the Rayleigh quotients of the columns of Q:
+            // wanted columns in [lo, hi], extra ones below bx (~ sigma_{r+1}^2)
+            double hi = 0.0, lo = 0.0, bx = 0.0;
+            {
+                double dg[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) dg[c] = Gy[c * 17];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    if (c < r) { hi = fmax(hi, dg[c]); lo = c == 0 ? dg[c] : fmin(lo, dg[c]); }
+                    else if (c < live) bx = fmax(bx, dg[c]);
+                }
+            }
+            hi_t = hi;
+            lo_t = lo;
+            last_power = power;
+            // Chebyshev only once the extra columns' estimate of sigma_{r+1}^2 has
+            // settled (2% between tests) and lies clearly below the wanted ones
+            const bool stable = bx_prev > 0.0 && fabs(bx - bx_prev) <= 0.02 * bx;
+            bx_prev = bx;
+            power = no_cheb || plain_next > 0 || !(bx > 0.0) || !(bx < 0.9 * lo) || !stable;
+            if (plain_next > 0) --plain_next;
+            if (power) {
+                cs = 0.0; es = 0.0;
+                scale = hi > 0.0 ? 1.0 / hi : 1.0;
+            } else {
+                cs = 0.5 * bx; es = 0.5 * bx;
+                sg1 = es / (hi - cs);
+                sg = sg1;
+                scale = sg1 / es;
+                // per-degree rate of the filter at the smallest wanted quotient,
+                // and the per-degree spread between the largest and smallest
+                // wanted ones (it costs the smaller wanted directions digits
+                // in the Cholesky QR that follows the sweep)
+                const double xr = (lo - cs) / es, xh = (hi - cs) / es;
+                const double glo = xr + __builtin_sqrt(fmax(xr * xr - 1.0, 0.0));
+                const double ghi = xh + __builtin_sqrt(fmax(xh * xh - 1.0, 0.0));
+                rate = 1.0 / glo;
+                spread = ghi / glo;
+            }
+            // residual of the first r columns over this workgroup's rows of Z
+            double part = 0.0;
+            for (int q = 0; q < ntl; ++q) {
+                const int b = 16 * (t0 + q) + (tid >> 4), c = tid & 15;
+                if (b < sJ && c < r) {
+                    double xr_[16], gc_[16];
+#pragma unroll
+                    for (int d = 0; d < 16; ++d) { xr_[d] = X[b * XS + d]; gc_[d] = Gy[d * 16 + c]; }
+                    double s = Zs[q * 256 + tid];
+#pragma unroll
+                    for (int d = 0; d < 16; ++d)
+                        if (d < r) s = __builtin_fma(-xr_[d], gc_[d], s);
+                    part = __builtin_fma(s, s, part);
+                }
+            }
+            part = block_sum(part, red);
+            if (tid == 0) st_dev(a.rp + wg, part);
+        }
+        // this workgroup's rows of the next block
+        double sgn = 0.0;
+        if (!test && !power) sgn = 1.0 / (2.0 / sg1 - sg);
+        for (int q = 0; q < ntl; ++q) {
+            const int e = q * 256 + tid, b = 16 * (t0 + q) + (tid >> 4);
+            const double xj = X[b * XS + (tid & 15)];
+            double xn;
+            if (test || power) xn = (Zs[e] - cs * xj) * scale;
+            else xn = (Zs[e] - cs * xj) * (2.0 * sgn / es) - (sg * sgn) * Xp[e];
+            Xp[e] = xj;
+            st_dev(a.Xr + (size_t)b * 16 + (tid & 15), b < sJ ? xn : 0.0);
+        }
+        if (!test && !power) sg = sgn;
+        CPHASE(6);
+        ++nbar;
+        grid_sync(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
+        CPHASE(7);
+        ++it;
+        if (test) {
+            double pn = 0.0;
+            for (int g = tid; g < G; g += NT) pn += ld_dev(a.rp + g);
+            // invariance residual of the wanted columns against the smallest
+            // wanted quotient (~ sigma_r^2), with a floor at the rounding of
+            // M^T M X (~ eps sigma_1^2)
+            const double num = __builtin_sqrt(block_sum(pn, red));
+            const double thr = fmax(tol_k * lo_t, 256.0 * 2.220446049250313e-16 * hi_t);
+            res = lo_t > 0.0 ? num / lo_t : (num > 0.0 ? 1.0 : 0.0);
+            conv = !(num > thr);
+#ifdef IRCUR_PHASE_PROFILE
+            // first launch of a run: the first eight tests (residual, applications, mode)
+            if (wg == 0 && tid == 0 && a.st->k_done == 0 && !a.prof_slot && ntest_ < 8) {
+                a.st->phase2[2 * ntest_] = __builtin_bit_cast(uint64_t, res);
+                a.st->phase2[2 * ntest_ + 1] = (uint64_t)(it * 1000 + m * 10 + (power ? 1 : 0));
+            }
+            ++ntest_;
+#endif
+            if (conv || it >= a.max_it) break;        // X still holds the tested Q
+            // a Chebyshev sweep that did not halve the residual: plain steps next
+            if (!last_power && res_sweep > 0.0 && res > res_sweep * __builtin_sqrt(pred)) no_cheb = true;
+            res_sweep = res;
+            // degree of the sweep: enough for the residual to reach tol at `rate`
+            m = 1;
+            if (!power) {
+                m = 8;
+                if (rate > 0.0 && rate < 1.0) m = (int)ceil(log(num / thr) / -log(rate));
+                // a sweep of degree m loses about eps res spread^m in the wanted
+                // directions: keep that a tenth of the tolerance
+                if (spread > 1.0) {
+                    const double room = 0.1 * tol_k / (2.220446049250313e-16 * fmax(res, 2.220446049250313e-16));
+                    const int mmax = room > 1.0 ? (int)floor(log(room) / log(spread)) : 1;
+                    m = min(m, max(1, mmax));
+                }
+                m = max(1, min(m, 8));
+            }
+            m = min(m, a.max_it - it);
+            pred = power ? 1.0 : pow(rate, (double)m);
+            j = 1;
+        } else {
+            ++j;
+        }
+        // all-gather the next block (one batch of loads per thread)
+        {
+            constexpr int B = 20;
+            const int tot = sJ16 * 16;
+            for (int e0 = tid; e0 < tot; e0 += NT * B) {
+                double v[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) v[u] = e0 + u * NT < tot ? ld_dev(a.Xr + e0 + u * NT) : 0.0;
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int e = e0 + u * NT;
+                    if (e < tot) X[(e >> 4) * XS + (e & 15)] = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        CPHASE(8);
+        if (j >= m) {
+            const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, Ls, Li, LiT, dead, scr,
+                                    a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
+            QADD(q);
+            test = true;
+        } else {
+            test = false;
+        }
+        CPHASE(9);
+    }
+    CPHASE(8);
+    // no barrier follows: the last workgroup out returns both counters to zero
+    // for the next launch
+    if (tid == 0) {
+        const uint32_t out = __hip_atomic_fetch_add(&a.st->bar_exit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (out == (uint32_t)G - 1) {
+            __hip_atomic_store(&a.st->bar_ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.st->bar_exit, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    // ---- epilogue -------------------------------------------------------------
+    // H = Y^T A_blk and Gamma' = B_k[:, J] Q from the partials of the last test
+    {
+        const int ix = ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15);
+        H[ix] = sum_parts(a.Gp + 256 + tid, 768, G);
+        Gam2[ix] = sum_parts(a.Gp + 512 + tid, 768, G);
+    }
+    // the next warm start keeps all columns (rows of this slice); the outputs use the first r
+    for (int e = tid; e < ntl * 256; e += NT) {
+        const int b = 16 * t0 + (e >> 4), c = e & 15;
+        a.prevV[b * 16 + c] = X[b * XS + c];
+    }
+    double bx = 0.0;
+    {
+        double dg[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) dg[c] = Gy[c * 17];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c >= r && c < live) bx = fmax(bx, dg[c]);
+    }
+    __syncthreads();
+    for (int e = tid; e < sJ16 * 16; e += NT)
+        if ((e & 15) >= r) X[(e >> 4) * XS + (e & 15)] = 0.0;
+    if ((tid & 15) >= r) Gam2[tid] = 0.0;
+    // Gy_rr = Ly Ly^T; a pivot <= s eps max_j Gy_jj is a direction the Gram
+    // matrix cannot resolve (sigma below about sqrt(s eps) sigma_1): dropped
+    const double ptol = (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
+    chol_inv<16>(Gy, Ls, Li, dead, ptol, r, LiT);
+    // Wt_blk = Y Ly^-T, Gamma = Ly^-1 H, TA = Ly^-T
+    double* Wb = Gs;
+    if (w4 == 0) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(l64 & 15) * 16 + 4 * ks + (l64 >> 4)],
+                                                       LiT[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = (l64 >> 4) + 4 * v;
+            Wb[row * 16 + (l64 & 15)] = row < nb ? acc[v] : 0.0;
+        }
+    }
+    {
+        const int i = tid >> 4, jj = tid & 15;
+        double li_[16], h_[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) { li_[k] = Li[i * 16 + k]; h_[k] = H[k * 16 + jj]; }
+        double g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g = __builtin_fma(li_[k], h_[k], g);
+        Gam[tid] = g;
+        TA[tid] = LiT[tid];
+    }
+    __syncthreads();
+    // Delta_blk = A_blk - Wt_blk Gamma (Wt_blk Gamma into Y)
+    if (w4 == 0) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wb[(l64 & 15) * 16 + 4 * ks + (l64 >> 4)],
+                                                       Gam[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Y[((l64 >> 4) + 4 * v) * 16 + (l64 & 15)] = acc[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * R; e += NT) {
+        const int ar = e / R, c = e - ar * R;
+        const int64_t base = (int64_t)(a0 + ar) * a.qs;
+        fput(a.rowI, base + c, Ab[ar * 16 + c], fd);
+        fput(a.rowI, base + R + c, Wb[ar * 16 + c], fd);
+        fput(a.rowI, base + 2 * R + c, Ab[ar * 16 + c] - Y[ar * 16 + c], fd);
+        a.W[(int64_t)(a0 + ar) * R + c] = Wb[ar * 16 + c];
+    }
+    // rows of this workgroup's slice: [B_k[:, J_b] | Q[b, :] | B_k[:, J_b] - Gamma' Q[b, :]^T]
+    for (int e = tid; e < ntl * 16 * R; e += NT) {
+        const int bl = e / R, c = e - bl * R;
+        const int b = 16 * t0 + bl;
+        if (b >= sJ) continue;
+        double g_[16], x_[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) { g_[i] = Gam2[c * 16 + i]; x_[i] = X[b * XS + i]; }
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s = __builtin_fma(g_[i], x_[i], s);
+        const int64_t base = (int64_t)b * a.qs;
+        const double bcj = Bsl[(bl >> 4) * 256 + (bl & 15) * 16 + c];
+        fput(a.rowJ, base + c, bcj, fd);
+        fput(a.rowJ, base + R + c, X[b * XS + c], fd);
+        fput(a.rowJ, base + 2 * R + c, bcj - s, fd);
+        a.V[(int64_t)b * R + c] = X[b * XS + c];
+    }
+    if (wg == 0) {
+        for (int e = tid; e < R * R; e += NT) {
+            const int c = e / R, d = e - c * R;
+            fput(a.GmI, e, Gam[c * 16 + d], fd);
+            fput(a.GmJ, e, Gam2[d * 16 + c], fd);
+            fput(a.scaleJ, e, TA[c * 16 + d], fd);
+            a.TAd[e] = TA[c * 16 + d];
+            a.sigma[e] = Ls[d * 16 + c];                               // Kc = Ly^T: H_r(M) = Wt Kc Q^T
+        }
+        // gap estimate sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr)),
+        // lambda_min(Gy_rr) = 1 / ||Ly^-1||_2^2 by power steps on Ly^-T Ly^-1
+        double gap = -1.0;
+        if (live > r && w4 == 0) {
+            double v = l64 < r ? 1.0 : 0.0, lam = 0.0;
+            for (int s = 0; s < 8; ++s) {
+                red[l64] = v;
+                __builtin_amdgcn_wave_barrier();
+                double w = 0.0;
+                if (l64 < 16) {
+                    double m_[16], v_[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) { m_[k] = Li[l64 * 16 + k]; v_[k] = red[k]; }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) w = __builtin_fma(m_[k], v_[k], w);
+                }
+                __builtin_amdgcn_wave_barrier();
+                red[l64] = w;
+                __builtin_amdgcn_wave_barrier();
+                double u = 0.0;
+                if (l64 < 16) {
+                    double m_[16], v_[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[l64 * 16 + k]; v_[k] = red[k]; }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) u = __builtin_fma(m_[k], v_[k], u);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const double nv = __builtin_sqrt(wave_sum_d(u * u));
+                const double vv = __builtin_sqrt(wave_sum_d(v * v));
+                lam = vv > 0.0 ? nv / vv : 0.0;
+                v = nv > 0.0 ? u / nv : 0.0;
+            }
+            gap = __builtin_sqrt(fmax(bx, 0.0) * lam);
+        }
+        if (tid == 0) {
+            int kept = 0, dd[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dd[i] = dead[i];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) kept += (i < r && dd[i] == 0) ? 1 : 0;
+            a.info->iters = it;
+            a.info->kept = kept;
+            a.info->resid = res;
+            a.info->gap = gap;
+            if (!conv) a.st->svd_capped = 1;
+            if (kept < r && Gy[0] > 0.0) a.st->rank_drop = 1;
+        }
+    }
+    CPHASE(10);
+#ifdef IRCUR_PHASE_PROFILE
+    if (wg == 0 && tid == 0) {
+        uint64_t* dst = a.prof_slot ? a.st->phase2 : a.st->phase;
+        for (int i = 0; i < 16; ++i) dst[i] += ph_[i];
+        (void)c_start; (void)r_start;
+    }
+#endif
+}
+
+hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s) {
+    const void* fn = nullptr;
+    int slot = -1;
+    if (dtype == 0) { fn = (const void*)csvd_kernel<double>; slot = 0; }
+    if (dtype == 1) { fn = (const void*)csvd_kernel<float>; slot = 1; }
+    if (dtype == 2) { fn = (const void*)csvd_kernel<bf16_t>; slot = 2; }
+    if (!fn || a.G < 1 || a.R > 16) return hipErrorInvalidValue;
+    static bool attr_set[3] = {false, false, false};
+    if (!attr_set[slot]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set[slot] = true;
+    }
+    CsvdArgs b = a;
+    void* args[] = {&b};
+    return hipLaunchKernel(fn, dim3(a.G), dim3(NT), args, lds_bytes, s);
+}
+
+}  // namespace ircur

@@ -45,8 +45,11 @@ struct DevState {
     int32_t rank_drop;   // a component of U^+ was dropped by the pinv rule
     double e_last;
     uint32_t bar_ctr;    // grid-barrier counter of the SVD kernel
-    uint32_t pad_;
+    uint32_t bar_exit;   // workgroups of the one-launch SVD past their last barrier
     uint64_t phase[16];  // phase timers (100 MHz ticks), only with IRCUR_PHASE_PROFILE
+    uint64_t phase2[16]; // the same for a repeated launch (profile builds)
+    int32_t prof_slot;   // which of the two the next launch accumulates into
+    int32_t pad2_;
 };
 
 // Per-iteration SVD diagnostics, one record per iteration.
@@ -154,6 +157,46 @@ struct SvdArgs {
     const double* Bsc;     // 16 x sJ16
     double* Zr;            // sJ16 x 16
     double* rp;            // G
+};
+
+// Core gather and top-r SVD in one launch (FP64 subspace arithmetic, R <= 16,
+// G = ceil(sI / 16) workgroups, each owning 16 rows of M).
+struct CsvdArgs {
+    const void* D; int64_t ldD;
+    const int32_t* I; const int32_t* J;
+    int32_t sI, sJ, r, R;
+    int64_t n1, n2;
+    const void* At;        // A_k^T (R x n1), factor dtype
+    const void* B;         // B_k (R x n2), factor dtype
+    double zeta; float zeta_f;
+    // the core [D - S_{k+1}]_{I,J} as written by the core kernel: row-tiled
+    // layout (see CoreArgs::MA) and compact A_k[I, :] (sI16 x 16), B_k[:, J]
+    // (16 x sJ16), zero padded
+    const double* MA;
+    const double* Abc;
+    const double* Bsc;
+    int32_t G;
+    int32_t max_it;        // cap on applications of M^T M
+    double tol;
+    double tol_e;          // > 0: the tolerance is max(tol, tol_e * e_k) (e_0 = 1)
+    int32_t warm;          // 0 random, 1 previous basis, 2 B_k[:, J]^T
+    uint64_t salt;
+    double* prevV;         // sJ16 x 16: basis of the previous launch (in: warm == 1; out)
+    double* Zp;            // G x sJ16 x 16 partials
+    double* Gp;            // G x 3 x 256 partials (Y^T Y, Y^T A_blk, B_k[:, J] Q)
+    double* Xr;            // sJ16 x 16: the next block (exchange)
+    double* rp;            // G residual parts
+    double* W;             // sI x R out: orthonormal left basis Wt
+    double* V;             // sJ x R out: orthonormal right basis Q
+    double* sigma;         // R x R out: Kc with H_r(M) = Wt Kc Q^T
+    void* rowI;            // sI x qs (factor dtype)
+    void* rowJ;            // sJ x qs
+    int32_t qs;
+    void* GmI; void* GmJ; void* scaleJ;
+    double* TAd;
+    SvdInfo* info;
+    DevState* st;
+    int32_t prof_slot;     // profile builds: phase timers of a repeated launch go to phase2
 };
 
 struct FinArgs {
@@ -271,6 +314,9 @@ hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
 int pass_nsplit(int dtype, int R, int s, int tiles);
 size_t pass_split_bytes(int dtype, int R);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+// Core gather and top-r SVD in one launch; its LDS bytes.
+hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s);
+size_t csvd_lds_bytes(int sJ, int G);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
 size_t svd_lds_bytes(int sJ, int bs16, int P);
 // LDS bytes of the variant that keeps its row block of M in LDS (P = 16).

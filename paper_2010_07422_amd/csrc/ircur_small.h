@@ -187,7 +187,7 @@ __device__ void mm_small(const double* A, int lda, const double* B, int ldb, dou
 // G may alias neither.
 template <int P>
 __device__ __forceinline__ void chol_inv(const double* G_, double* L_, double* Linv_, int* dead, double tol,
-                                         int live = P) {
+                                         int live = P, double* LinvT_ = nullptr) {
     static_assert(P >= 2 && P <= 64 && P % 2 == 0, "one wave holds the P rows");
     const ldouble* G = lp(G_);
     ldouble* L = lp(L_);
@@ -244,6 +244,7 @@ __device__ __forceinline__ void chol_inv(const double* G_, double* L_, double* L
             for (int k = 0; k < P; ++k) {
                 L[i * P + k] = (k < i && k < live) ? a[k] : ((k == i) ? pii : 0.0);
                 Linv[k * P + i] = (i <= k && k < live) ? x[k] : 0.0;
+                if (LinvT_) lp(LinvT_)[i * P + k] = (i <= k && k < live) ? x[k] : 0.0;
             }
         }
     }

@@ -80,6 +80,7 @@ _SIGS = {
     "ircur_sample": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_int32, ctypes.c_int32, _I32P, _I32P]),
     "ircur_get_phase_profile": (ctypes.c_int, [_P, _DP]),
+    "ircur_get_phase_profile2": (ctypes.c_int, [_P, _DP]),
     "ircur_unrolled_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(Instance), ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P]),
     "ircur_unrolled_forward": (ctypes.c_int, [_P, _P, _P]),
@@ -383,9 +384,10 @@ class IRCUR:
                                             int(reps), ctypes.byref(us)), "ircur_time_sparse")
         return us.value
 
-    def phase_profile(self):
+    def phase_profile(self, second=False):
         buf = (ctypes.c_double * 16)()
-        self._check(lib().ircur_get_phase_profile(self.h, buf), "ircur_get_phase_profile")
+        name = "ircur_get_phase_profile2" if second else "ircur_get_phase_profile"
+        self._check(getattr(lib(), name)(self.h, buf), name)
         return list(buf)
 
     def _sync_stream(self):

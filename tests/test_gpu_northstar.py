@@ -128,15 +128,27 @@ def test_video_76800x1200_f32_full_trajectory():
     print("gpu iters", it, "e", e, "oracle iters", ref.k, "e", ref.e_hist[-1], flush=True)
     assert it == ref.k and e <= 1e-5
     assert np.array_equal(I, ref.I) and np.array_equal(J, ref.J)
-    herr = np.abs(h - ref.e_hist) / np.array(ref.e_hist)
-    print("e history max rel diff", herr.max(), flush=True)
-    assert herr.max() <= 1e-3
+    # e history: 1e-3 relative, plus an absolute floor for the FP32 rounding of
+    # the entries of D - L that make up its numerator (~ 2 eps_32 max|D|)
+    eps32 = 2.0 ** -23
+    dmax = float(np.abs(v.D).max())
+    hdiff = np.abs(h - ref.e_hist)
+    print("e history max rel diff", (hdiff / np.array(ref.e_hist)).max(), flush=True)
+    assert np.all(hdiff <= 1e-3 * np.array(ref.e_hist) + 2 * eps32 * dmax)
     dL = O.factored_rel_diff(A, B, ref.A, ref.B)
     print("L rel diff", dL, "vs background", O.factored_rel_diff(A, B, v.F, v.G.T), flush=True)
     assert dL <= 1e-5
     zeta = Lmax * cfg["gamma"] ** (it - 1)
+    # a threshold decision is pinned only where |x| stays clear of zeta by more
+    # than the two runs' entrywise difference in L on the sampled blocks (taken
+    # from their final factors) plus the FP32 rounding of x
+    dLI = np.abs(A[I] @ B - ref.A[I] @ ref.B).max()
+    dLJ = np.abs(A @ B[:, J] - ref.A @ ref.B[:, J]).max()
+    band = 2.0 * max(dLI, dLJ) + 4 * eps32 * dmax
+    print("entrywise L difference on the blocks", dLI, dLJ, "band", band, flush=True)
     for S_g, S_o, X_o in ((SI, ref.last["S_I"], ref.last["X_I"]), (SJ, ref.last["S_J"], ref.last["X_J"])):
-        bad, flips = _mask_agrees(S_g, S_o, X_o, zeta, 1e-4 * zeta + 1e-6)
+        bad, flips = _mask_agrees(S_g, S_o, X_o, zeta, band)
+        print("support flips", flips, "outside the band", bad, "of", S_o.size, flush=True)
         assert bad == 0, flips
         assert _rel(S_g, S_o) <= 1e-5
 

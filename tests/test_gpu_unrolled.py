@@ -120,17 +120,30 @@ def test_G2_central_differences_on_device():
     dz = ub.backward().cpu().numpy()
     fd = np.zeros(K)
     floor = np.zeros(K)
-    for k in range(K):
-        h = 1e-5 * zetas[k]
+
+    def quotient(k, h):
         zp, zm = zetas.copy(), zetas.copy()
         zp[k] += h
         zm[k] -= h
         lp = float(ub.forward(torch.tensor(zp)).sum())
+        l0a = float(ub.forward(torch.tensor(zetas)).sum())
         lm = float(ub.forward(torch.tensor(zm)).sum())
-        fd[k] = (lp - lm) / (zp[k] - zm[k])
-        # round-off of the difference quotient: a few ulps of the loss over 2h
-        # (the forward's SVDs stop at 1e-13 relative, which sets the ulp count)
-        floor[k] = 1e3 * 2.0 ** -52 * (abs(lp) + abs(lm)) / (zp[k] - zm[k])
+        l0b = float(ub.forward(torch.tensor(zetas)).sum())
+        # noise of the difference: each forward's SVDs stop at their tolerance
+        # from the subspace the previous forward left, so the loss at the same
+        # zeta moves with the warm start; measured as the spread of two
+        # evaluations at zeta (after the + and after the - step), plus round-off
+        noise = abs(l0a - l0b) + 1e3 * 2.0 ** -52 * (abs(lp) + abs(lm))
+        return (lp - lm) / (zp[k] - zm[k]), 2.0 * noise / (zp[k] - zm[k])
+
+    for k in range(K):
+        # central differences at h and h/2 combined by Richardson extrapolation
+        # (the h^2 term of the truncation error cancels)
+        h = 1e-4 * zetas[k]
+        d1, n1 = quotient(k, h)
+        d2, n2 = quotient(k, 0.5 * h)
+        fd[k] = (4.0 * d2 - d1) / 3.0
+        floor[k] = (4.0 * n2 + n1) / 3.0
     err = np.abs(fd - dz) / np.abs(dz)
     print("fd", fd, "adjoint", dz, "per-component rel err", err, "floor", floor, flush=True)
     # each component on its own scale: |fd_k - dz_k| <= 1e-6 |dz_k| + round-off floor
