@@ -27,6 +27,14 @@ FLAGS = [
 ]
 
 
+# Per-source device flags: the one-launch SVD keeps its matrix-core
+# accumulators in ordinary vector registers (no copies to and from the
+# accumulation registers around every product in its loops).
+SRC_FLAGS = {
+    "ircur_csvd.hip": ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines()
@@ -47,7 +55,8 @@ def build(verbose: bool = False, jobs: int = 3, out: str | None = None,
 
     def comp(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, *("-D" + d for d in defines), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *SRC_FLAGS.get(src, ()), *("-D" + d for d in defines), "-c", os.path.join(CSRC, src),
+               "-o", obj]
         out = _run(cmd)
         if verbose and out.strip():
             print(out)

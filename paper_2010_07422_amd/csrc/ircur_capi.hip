@@ -177,6 +177,7 @@ struct ircur_ctx {
     bool lds_svd = false;           // the SVD keeps its block of M in LDS (P = 16)
     bool csvd = false;              // core gather and SVD in one launch (ircur_csvd.hip)
     int Gc = 0;                     // its workgroups, ceil(sI / 16)
+    int Xs = 1;                     // their stride in the grid (all on one XCD when it fits)
     size_t csvd_lds = 0;
     double* Xr = nullptr;           // its exchange block (sJ16 x 16)
     int32_t* Icur = nullptr;        // index sets of an export (device)
@@ -416,6 +417,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
         ka.At = c->At[cur]; ka.B = c->B[cur];
         ka.MA = c->MA; ka.Abc = c->Abc; ka.Bsc = c->Bsc;
         ka.G = c->Gc;
+        ka.xs = c->Xs;
         ka.max_it = p.svd_max_it > 0 ? p.svd_max_it : 256;
         ka.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : (p.dtype == IRCUR_F32 ? 1e-9 : 1e-7));
         ka.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
@@ -633,6 +635,15 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
             c->csvd = true;
             c->Gc = gc;
             c->csvd_lds = csvd_lds_bytes(p.sJ, gc);
+            // workgroups are dispatched to the XCDs in turn: a stride of the XCD
+            // count puts the G working ones on one XCD (one per compute unit),
+            // so their exchanges and barriers stay in that XCD's L2
+            int nx = 1;
+            if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) nx = 1;
+            c->Xs = (nx > 1 && gc * nx <= ncu) ? nx : 1;
+#ifdef IRCUR_PHASE_PROFILE
+            if (std::getenv("IRCUR_SPREAD")) c->Xs = 1;
+#endif
         }
     }
     c->stream = (hipStream_t)stream;

@@ -35,7 +35,7 @@
 // Data exchanged between workgroups uses device-scope stores and loads, so
 // the barriers need no cache-wide fence.  Every workgroup holds the reduced
 // small matrices and takes identical decisions.
-#include "ircur_small.h"
+#include "ircur_block16.h"
 #include "ircur_device.h"
 
 #include <stdint.h>
@@ -81,17 +81,38 @@ __device__ void grid_sync(uint32_t* ctr, uint32_t target, int32_t* fail) {
 
 // Sum over the G partials of one 256-double block (block index `blk` of each
 // partial, partials `pstride` doubles apart), thread t summing entry t in
-// partial order; loads issued 16 at a time.
+// partial order; loads issued 32 at a time (one round trip for G <= 32).
 __device__ __forceinline__ double sum_parts(const double* base, size_t pstride, int G) {
     double s = 0.0;
-    for (int g0 = 0; g0 < G; g0 += 16) {
-        double v[16];
+    for (int g0 = 0; g0 < G; g0 += 32) {
+        double v[32];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = g0 + u < G ? ld_dev(base + (size_t)(g0 + u) * pstride) : 0.0;
+        for (int u = 0; u < 32; ++u) v[u] = g0 + u < G ? ld_dev(base + (size_t)(g0 + u) * pstride) : 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += v[u];
+        for (int u = 0; u < 32; ++u) s += v[u];
     }
     return s;
+}
+
+// Two such sums with their loads issued together (32 of each at a time).
+__device__ __forceinline__ void sum_parts2(const double* b1, size_t s1, const double* b2, size_t s2, int G, double& r1,
+                                           double& r2) {
+    double x = 0.0, y = 0.0;
+    for (int g0 = 0; g0 < G; g0 += 32) {
+        double v[32], w[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            v[u] = g0 + u < G ? ld_dev(b1 + (size_t)(g0 + u) * s1) : 0.0;
+            w[u] = g0 + u < G ? ld_dev(b2 + (size_t)(g0 + u) * s2) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            x += v[u];
+            y += w[u];
+        }
+    }
+    r1 = x;
+    r2 = y;
 }
 
 }  // namespace
@@ -116,63 +137,18 @@ struct QTimes { uint64_t g, c, x; };
 // the column-tiled reads of M^T Y fall on distinct banks.
 __device__ __forceinline__ int mb_index(int row, int col) { return (col >> 2) * 68 + (col & 3) * 17 + row; }
 
-// The block X (|J| x 16) in LDS with a row stride of 17 doubles (the reads of
-// a 16-row tile by rows and by columns both avoid bank conflicts).
-constexpr int XS = 17;
-
 namespace {
 
-// G = X^T X over the first 4 KS rows of X: k-steps split over the four
-// waves, each with two accumulator chains; partial tiles summed in order.
-__device__ __forceinline__ void gram16(const double* X, int KS, double* scr, double* G) {
-    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-    const int per = (KS + 3) >> 2;
-    const int k0 = min(KS, w * per), k1 = min(KS, (w + 1) * per);
-    d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-    for (int ks = k0; ks < k1; ks += 2) {
-        const bool two = ks + 1 < k1;
-        const double x1 = X[(4 * ks + (l >> 4)) * XS + (l & 15)];
-        const double x2 = two ? X[(4 * (ks + 1) + (l >> 4)) * XS + (l & 15)] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, acc, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, x2, acc2, 0, 0, 0);
-    }
-    acc += acc2;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) scr[w * 256 + ((l >> 4) + 4 * v) * 16 + (l & 15)] = acc[v];
-    __syncthreads();
-    G[tid] = ((scr[tid] + scr[256 + tid]) + scr[512 + tid]) + scr[768 + tid];
-    __syncthreads();
-}
-
-// X <- X T for the row tiles of X (T 16 x 16 row-major in LDS), in place:
-// each tile's rows are read before they are written.
-__device__ __forceinline__ void xmul16(double* X, int ntiles, const double* T) {
-    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
-    for (int t = w; t < ntiles; t += 4) {
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        double av[4], bv[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            av[ks] = X[(16 * t + (l & 15)) * XS + 4 * ks + (l >> 4)];
-            bv[ks] = T[(4 * ks + (l >> 4)) * 16 + (l & 15)];
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc, 0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) X[(16 * t + (l >> 4) + 4 * v) * XS + (l & 15)] = acc[v];
-    }
-    __syncthreads();
-}
-
 // Cholesky QR of the first `live` columns of X (rows >= rows_valid zero):
-// X <- X L^-T with X^T X = L L^T, on the column-equilibrated Gram matrix
-// (columns scaled to unit norm first: a column that is merely small after a
-// power step is not mistaken for a dependent one).  A second pass runs when the first pivots
-// spread by more than `kappa2_one` in squared condition (its rounding of
-// X^T X would show in the orthogonality) and whenever a column was found
-// dependent (refilled with pseudo-random entries); at most four passes.
+// X <- X L^-T with X^T X = L L^T.  A column is dead when its pivot falls to
+// 1e-14 of its own squared norm (a column that is merely small after a power
+// step is not mistaken for a dependent one).  A second pass runs when the
+// first pivots, relative to the column norms, spread by more than
+// `kappa2_one` (the rounding of X^T X would show in the orthogonality) and
+// whenever a column was found dependent (refilled with pseudo-random
+// entries); at most four passes.  Gs, LiT: 16 x XS; st: 4; scr: 4 x 256.
 __device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, int live, double kappa2_one, int min_passes,
-                         double* Gs, double* Ls, double* Li, double* LiT, int* dead, double* scr, uint64_t salt) {
+                                         double* Gs, double* LiT, int* dead, double* st, double* scr, uint64_t salt) {
     const int KS = sJ16 / 4, nt = sJ16 / 16;
     int need = min_passes;
     QTimes qt = {0, 0, 0};
@@ -184,43 +160,13 @@ __device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, in
 #endif
     for (int pass = 0; pass < 4; ++pass) {
         gram16(X, KS, scr, Gs);
-        // Gs <- D^-1 Gs D^-1, D = diag(column norms)
-        {
-            const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-            const double di = Gs[i * 17], dj = Gs[j * 17];
-            const double si = di > 0.0 ? rsqrt_d(di) : 0.0, sj = dj > 0.0 ? rsqrt_d(dj) : 0.0;
-            const double g = Gs[threadIdx.x] * si * sj;
-            __syncthreads();
-            Gs[threadIdx.x] = g;
-            scr[threadIdx.x] = si;      // row scale of the transform (read below as scr[16 * i])
-            __syncthreads();
-        }
         QPHASE(g);
-        chol_inv<16>(Gs, Ls, Li, dead, 1e-14, live, LiT);
-        // transform D^-1 L^-T: row k of L^-T scaled by 1 / norm of column k
-        {
-            const int k = threadIdx.x >> 4;
-            LiT[threadIdx.x] *= scr[k * 16];
-            __syncthreads();
-        }
+        chol16(Gs, XS, live, 1e-14, true, nullptr, LiT, dead, st, scr);
         QPHASE(c);
         xmul16(X, nt, LiT);
         QPHASE(x);
-        int nd = 0;
-        double pmax = 0.0, pmin = 0.0;
-        {
-            double dg[16];
-            int dd[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) { dg[j] = Ls[j * 17]; dd[j] = dead[j]; }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (j >= live) continue;
-                nd += dd[j];
-                if (!dd[j]) { pmax = fmax(pmax, dg[j]); pmin = pmin == 0.0 ? dg[j] : fmin(pmin, dg[j]); }
-            }
-        }
-        if (pass == 0 && pmin > 0.0 && (pmax / pmin) * (pmax / pmin) > kappa2_one) need = max(need, 2);
+        const int nd = (int)st[0];
+        if (pass == 0 && st[2] > 0.0 && st[1] > kappa2_one * st[2]) need = max(need, 2);
         if (nd > 0) {
             need = max(need, pass + 2);
             for (int e = threadIdx.x; e < rows_valid * 16; e += NT) {
@@ -245,7 +191,7 @@ size_t csvd_lds_bytes(int sJ, int G) {
     d += sJ16 * XS;                   // X
     d += 3 * tpg * 256;               // X_{j-1} slice, reduced Z slice, B_k[:, J] of the slice
     d += 2 * 256;                     // Y, A_k[I_blk, :]
-    d += 10 * 256;                    // Gy, H, Gs, Ls, Li, LiT, Gam, Gam2, TA, spare
+    d += 10 * 256;                    // Gy, H, Gs, Ls, LiT (16 x 17), Gam, Gam2, TA, statistics
     d += 4 * 256;                     // MFMA scratch
     d += 64;                          // reduction buffer
     return d * sizeof(double) + 96 * sizeof(int);
@@ -254,10 +200,10 @@ size_t csvd_lds_bytes(int sJ, int G) {
 template <typename T>
 __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     typedef typename FactorOf<T>::type F;
-    if (a.st->stop) return;
+    if (blockIdx.x % a.xs) return;
     extern __shared__ double smem[];
-    const int tid = threadIdx.x, l64 = tid & 63, w4 = tid >> 6;
-    const int wg = blockIdx.x, G = a.G;
+    const int tid = threadIdx.x, l64 = tid & 63, w4 = wave_id();
+    const int wg = blockIdx.x / a.xs, G = a.G;
 #ifdef IRCUR_PHASE_PROFILE
     uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
     const uint64_t c_start = __builtin_amdgcn_s_memtime(), r_start = t_prev;
@@ -281,10 +227,6 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     const int live = min(16, sJ);         // columns of the block with a direction to hold
     const int64_t n1 = a.n1, n2 = a.n2;
     const int fd = sizeof(F) == 8 ? 0 : 1;
-    // a single Cholesky QR pass keeps X^T X within about 16 eps kappa^2 of I
-    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
-    const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
-    const int min_passes = 1;
 
     double* Mb = smem;                    // 16 x sJ16 at mb_index(row, col)
     double* X = Mb + 17 * sJ16;           // sJ16 x 16, row stride XS
@@ -293,16 +235,16 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     double* Bsl = Zs + tpg * 256;         // tpg x 256: B_k[c, J_b] at [b_local * 16 + c]
     double* Y = Bsl + tpg * 256;          // 16 x 16
     double* Ab = Y + 256;                 // 16 x 16
-    double* Gy = Ab + 256;
+    double* Gy = Ab + 256;                // small matrices: 10 x 256 doubles
     double* H = Gy + 256;
-    double* Gs = H + 256;
-    double* Ls = Gs + 256;
-    double* Li = Ls + 256;
-    double* LiT = Li + 256;
-    double* Gam = LiT + 256;
+    double* Gs = H + 256;                 // 16 x XS
+    double* Ls = Gs + 16 * XS;            // 16 x XS
+    double* LiT = Ls + 16 * XS;           // 16 x XS
+    double* Gam = LiT + 16 * XS;
     double* Gam2 = Gam + 256;
     double* TA = Gam2 + 256;
-    double* scr = TA + 512;               // 4 x 256 (one spare block before it)
+    double* cst = TA + 256;               // 16: Cholesky statistics
+    double* scr = Gy + 10 * 256;          // 4 x 256
     double* red = scr + 4 * 256;          // 64
     int* dead = (int*)(red + 64);         // 64
     int* Il = dead + 64;                  // 16
@@ -317,19 +259,15 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         constexpr int UL = 32;            // doubles per thread (|J| <= 512)
         double mv[UL];
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-            const int e = tid + NT * u;
-            mv[u] = e < KS * 64 ? src[e] : 0.0;
-        }
+        for (int u = 0; u < UL; ++u) mv[u] = src[min(tid + NT * u, KS * 64 - 1)];   // (clamped: no branch per load)
         const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
         // B_k[c, J_b] (compact, 16 x sJ16) into X[b][c]
         double bv[18];
 #pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            const int e = tid + NT * u, c = e / sJ16, b = e - c * sJ16;
-            bv[u] = c < 16 ? a.Bsc[e] : 0.0;
-            (void)b;
-        }
+        for (int u = 0; u < 18; ++u) bv[u] = a.Bsc[min(tid + NT * u, 16 * sJ16 - 1)];
+        // the run state is read with the loads above in flight; a stopped run
+        // returns before it writes anything
+        if (a.st->stop) return;
 #pragma unroll
         for (int u = 0; u < UL; ++u) {
             const int e = tid + NT * u;
@@ -350,6 +288,10 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         }
     }
     __syncthreads();
+    // a single Cholesky QR pass keeps X^T X within about 16 eps kappa^2 of I
+    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
+    const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
+    const int min_passes = 1;
     // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
     for (int e = tid; e < ntl * 256; e += NT) {
         const int b = 16 * t0 + (e >> 4), c = e & 15;
@@ -369,7 +311,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     __syncthreads();
     CPHASE(0);
     {
-        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, a.warm == 1 ? 1 : min_passes, Gs, Ls, Li, LiT, dead,
+        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, a.warm == 1 ? 1 : min_passes, Gs, LiT, dead, cst,
                                 scr, a.salt + 17);
         QADD(q);
     }
@@ -395,57 +337,85 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     double pred = 1.0;          // residual factor predicted for the current sweep
     double hi_t = 0.0, lo_t = 0.0;   // largest and smallest wanted quotients at the last test
     for (;;) {
-        // Y = M_blk X: k-steps split over the four waves, partial tiles summed in order
+        // Y = M_blk X: wave w takes the k-steps w, w + 4, ... (ntj of them), the
+        // operands of each pair requested before the products of the pair
+        // before; the four partial tiles summed in wave order.  Every wave ends
+        // with Y in the B-operand layout, yb[ks] = Y[4 ks + l/16][l % 16].
+        double yb[4];
         {
-            const int per = (KS + 3) >> 2;
-            const int k0 = min(KS, w4 * per), k1 = min(KS, (w4 + 1) * per);
+            constexpr int ST = 272;           // 4 k-steps further on, in both layouts
+            const ldouble* mp = lp(Mb) + w4 * 68 + (l64 >> 4) * 17 + (l64 & 15);
+            const ldouble* xp = lp(X) + (4 * w4 + (l64 >> 4)) * XS + (l64 & 15);
+            const int n = ntj;
             d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-            for (int ks = k0; ks < k1; ks += 4) {
-                double av[4], bv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool in = ks + u < k1;
-                    av[u] = in ? Mb[mb_index(l64 & 15, 4 * (ks + u) + (l64 >> 4))] : 0.0;
-                    bv[u] = in ? X[(4 * (ks + u) + (l64 >> 4)) * XS + (l64 & 15)] : 0.0;
-                }
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], acc, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], acc2, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], acc, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], acc2, 0, 0, 0);
+            double a0 = mp[0], b0 = xp[0], a1 = mp[min(1, n - 1) * ST], b1 = xp[min(1, n - 1) * ST];
+            for (int u = 0; u < n; u += 2) {
+                const int u2 = min(u + 2, n - 1), u3 = min(u + 3, n - 1);
+                const double na0 = mp[u2 * ST], nb0 = xp[u2 * ST], na1 = mp[u3 * ST], nb1 = xp[u3 * ST];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(u + 1 < n ? a1 : 0.0, b1, acc2, 0, 0, 0);
+                a0 = na0; b0 = nb0; a1 = na1; b1 = nb1;
             }
             acc += acc2;
+            ldouble* sc = lp(scr);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) scr[w4 * 256 + ((l64 >> 4) + 4 * v) * 16 + (l64 & 15)] = acc[v];
+            for (int v = 0; v < 4; ++v) sc[w4 * 256 + ((l64 >> 4) + 4 * v) * 16 + (l64 & 15)] = acc[v];
             __syncthreads();
-            Y[tid] = ((scr[tid] + scr[256 + tid]) + scr[512 + tid]) + scr[768 + tid];
-            __syncthreads();
-        }
-        CPHASE(2);
-        // partial Z_g = M_blk^T Y (tile-lane order); on a test also the partial
-        // Grams Y^T Y, Y^T A_blk and Gamma'_g = B_k[:, J_slice] X_slice
-        for (int tj = w4; tj < ntj; tj += 4) {
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            const double* mcol = Mb + mb_index(l64 >> 4, 16 * tj + (l64 & 15));
-            double av[4], bv[4];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                av[ks] = mcol[4 * ks];
-                bv[ks] = Y[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)];
+                const int e = (4 * ks + (l64 >> 4)) * 16 + (l64 & 15);
+                yb[ks] = ((sc[e] + sc[256 + e]) + sc[512 + e]) + sc[768 + e];
             }
+            if (w4 == 0) {
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[ks], acc, 0, 0, 0);
+                for (int ks = 0; ks < 4; ++ks) lp(Y)[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)] = yb[ks];
+            }
+        }
+        CPHASE(2);
+        // partial Z_g = M_blk^T Y (tile-lane order), wave w taking the tiles
+        // w, w + 4, ... two at a time; on a test also the partial Grams Y^T Y,
+        // Y^T A_blk and Gamma'_g = B_k[:, J_slice] X_slice
+        {
+            const ldouble* mc = lp(Mb) + mb_index(l64 >> 4, l64 & 15);
+            for (int tj = w4; tj < ntj; tj += 8) {
+                const int tk = tj + 4;
+                const bool two = tk < ntj;
+                double av[4], cv[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) st_dev(Zp + (size_t)tj * 256 + v * 64 + l64, acc[v]);
+                for (int ks = 0; ks < 4; ++ks) {
+                    av[ks] = mc[tj * 272 + 4 * ks];
+                    cv[ks] = mc[(two ? tk : tj) * 272 + 4 * ks];
+                }
+                d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+                if (two) {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], yb[ks], acc, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(cv[ks], yb[ks], acc2, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        st_dev(Zp + (size_t)tj * 256 + v * 64 + l64, acc[v]);
+                        st_dev(Zp + (size_t)tk * 256 + v * 64 + l64, acc2[v]);
+                    }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], yb[ks], acc, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) st_dev(Zp + (size_t)tj * 256 + v * 64 + l64, acc[v]);
+                }
+            }
         }
         if (test && w4 < 3) {
             d4 acc = {0.0, 0.0, 0.0, 0.0};
-            if (w4 < 2) {
-                const double* Bop = w4 == 0 ? Y : Ab;
+            if (w4 == 0) {
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int e = (4 * ks + (l64 >> 4)) * 16 + (l64 & 15);
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[e], Bop[e], acc, 0, 0, 0);
-                }
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[ks], yb[ks], acc, 0, 0, 0);
+            } else if (w4 == 1) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[ks], Ab[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)], acc,
+                                                               0, 0, 0);
             } else {
                 for (int q = 0; q < ntl; ++q)
 #pragma unroll
@@ -462,11 +432,21 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         ++nbar;
         grid_sync(&a.st->bar_ctr, nbar * (uint32_t)G, &a.st->svd_fail);
         CPHASE(4);
-        // reduce: Gy (test) in full, this workgroup's row tiles of Z
-        if (test) Gy[((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15)] = sum_parts(a.Gp + tid, 768, G);
-        for (int q = 0; q < ntl; ++q)
-            Zs[q * 256 + ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15)] =
-                sum_parts(a.Zp + (size_t)(t0 + q) * 256 + tid, (size_t)sJ16 * 16, G);
+        // reduce: Gy (test) in full and this workgroup's row tiles of Z, the
+        // loads of Gy and of the first tile in one batch
+        {
+            const int ix = ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15);
+            if (test && ntl >= 1) {
+                double g, z;
+                sum_parts2(a.Gp + tid, 768, a.Zp + (size_t)t0 * 256 + tid, (size_t)sJ16 * 16, G, g, z);
+                Gy[ix] = g;
+                Zs[ix] = z;
+            } else {
+                if (test) Gy[ix] = sum_parts(a.Gp + tid, 768, G);
+                if (ntl >= 1) Zs[ix] = sum_parts(a.Zp + (size_t)t0 * 256 + tid, (size_t)sJ16 * 16, G);
+            }
+            for (int q = 1; q < ntl; ++q) Zs[q * 256 + ix] = sum_parts(a.Zp + (size_t)(t0 + q) * 256 + tid, (size_t)sJ16 * 16, G);
+        }
         __syncthreads();
         CPHASE(5);
         if (test) {
@@ -525,7 +505,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
                     part = __builtin_fma(s, s, part);
                 }
             }
-            part = block_sum(part, red);
+            part = block_sum_dpp(part, red);
             if (tid == 0) st_dev(a.rp + wg, part);
         }
         // this workgroup's rows of the next block
@@ -552,7 +532,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             // invariance residual of the wanted columns against the smallest
             // wanted quotient (~ sigma_r^2), with a floor at the rounding of
             // M^T M X (~ eps sigma_1^2)
-            const double num = __builtin_sqrt(block_sum(pn, red));
+            const double num = __builtin_sqrt(block_sum_dpp(pn, red));
             const double thr = fmax(tol_k * lo_t, 256.0 * 2.220446049250313e-16 * hi_t);
             res = lo_t > 0.0 ? num / lo_t : (num > 0.0 ? 1.0 : 0.0);
             conv = !(num > thr);
@@ -606,7 +586,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         __syncthreads();
         CPHASE(8);
         if (j >= m) {
-            const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, Ls, Li, LiT, dead, scr,
+            const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, LiT, dead, cst, scr,
                                     a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
             QADD(q);
             test = true;
@@ -630,8 +610,10 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     // H = Y^T A_blk and Gamma' = B_k[:, J] Q from the partials of the last test
     {
         const int ix = ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15);
-        H[ix] = sum_parts(a.Gp + 256 + tid, 768, G);
-        Gam2[ix] = sum_parts(a.Gp + 512 + tid, 768, G);
+        double h, g2;
+        sum_parts2(a.Gp + 256 + tid, 768, a.Gp + 512 + tid, 768, G, h, g2);
+        H[ix] = h;
+        Gam2[ix] = g2;
     }
     // the next warm start keeps all columns (rows of this slice); the outputs use the first r
     for (int e = tid; e < ntl * 256; e += NT) {
@@ -648,13 +630,13 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             if (c >= r && c < live) bx = fmax(bx, dg[c]);
     }
     __syncthreads();
-    for (int e = tid; e < sJ16 * 16; e += NT)
-        if ((e & 15) >= r) X[(e >> 4) * XS + (e & 15)] = 0.0;
+    for (int e = tid; e < ntl * 256; e += NT)              // (only the slice rows are read below)
+        if ((e & 15) >= r) X[(16 * t0 + (e >> 4)) * XS + (e & 15)] = 0.0;
     if ((tid & 15) >= r) Gam2[tid] = 0.0;
     // Gy_rr = Ly Ly^T; a pivot <= s eps max_j Gy_jj is a direction the Gram
     // matrix cannot resolve (sigma below about sqrt(s eps) sigma_1): dropped
     const double ptol = (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
-    chol_inv<16>(Gy, Ls, Li, dead, ptol, r, LiT);
+    chol16(Gy, 16, r, ptol, false, Ls, LiT, dead, nullptr, scr);
     // Wt_blk = Y Ly^-T, Gamma = Ly^-1 H, TA = Ly^-T
     double* Wb = Gs;
     if (w4 == 0) {
@@ -662,7 +644,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(l64 & 15) * 16 + 4 * ks + (l64 >> 4)],
-                                                       LiT[(4 * ks + (l64 >> 4)) * 16 + (l64 & 15)], acc, 0, 0, 0);
+                                                       LiT[(4 * ks + (l64 >> 4)) * XS + (l64 & 15)], acc, 0, 0, 0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = (l64 >> 4) + 4 * v;
@@ -673,12 +655,12 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         const int i = tid >> 4, jj = tid & 15;
         double li_[16], h_[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) { li_[k] = Li[i * 16 + k]; h_[k] = H[k * 16 + jj]; }
+        for (int k = 0; k < 16; ++k) { li_[k] = LiT[k * XS + i]; h_[k] = H[k * 16 + jj]; }
         double g = 0.0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) g = __builtin_fma(li_[k], h_[k], g);
         Gam[tid] = g;
-        TA[tid] = LiT[tid];
+        TA[tid] = LiT[i * XS + jj];
     }
     __syncthreads();
     // Delta_blk = A_blk - Wt_blk Gamma (Wt_blk Gamma into Y)
@@ -725,42 +707,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             fput(a.GmJ, e, Gam2[d * 16 + c], fd);
             fput(a.scaleJ, e, TA[c * 16 + d], fd);
             a.TAd[e] = TA[c * 16 + d];
-            a.sigma[e] = Ls[d * 16 + c];                               // Kc = Ly^T: H_r(M) = Wt Kc Q^T
-        }
-        // gap estimate sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr)),
-        // lambda_min(Gy_rr) = 1 / ||Ly^-1||_2^2 by power steps on Ly^-T Ly^-1
-        double gap = -1.0;
-        if (live > r && w4 == 0) {
-            double v = l64 < r ? 1.0 : 0.0, lam = 0.0;
-            for (int s = 0; s < 8; ++s) {
-                red[l64] = v;
-                __builtin_amdgcn_wave_barrier();
-                double w = 0.0;
-                if (l64 < 16) {
-                    double m_[16], v_[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) { m_[k] = Li[l64 * 16 + k]; v_[k] = red[k]; }
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) w = __builtin_fma(m_[k], v_[k], w);
-                }
-                __builtin_amdgcn_wave_barrier();
-                red[l64] = w;
-                __builtin_amdgcn_wave_barrier();
-                double u = 0.0;
-                if (l64 < 16) {
-                    double m_[16], v_[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[l64 * 16 + k]; v_[k] = red[k]; }
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) u = __builtin_fma(m_[k], v_[k], u);
-                }
-                __builtin_amdgcn_wave_barrier();
-                const double nv = __builtin_sqrt(wave_sum_d(u * u));
-                const double vv = __builtin_sqrt(wave_sum_d(v * v));
-                lam = vv > 0.0 ? nv / vv : 0.0;
-                v = nv > 0.0 ? u / nv : 0.0;
-            }
-            gap = __builtin_sqrt(fmax(bx, 0.0) * lam);
+            a.sigma[e] = Ls[d * XS + c];                               // Kc = Ly^T: H_r(M) = Wt Kc Q^T
         }
         if (tid == 0) {
             int kept = 0, dd[16];
@@ -771,10 +718,48 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             a.info->iters = it;
             a.info->kept = kept;
             a.info->resid = res;
-            a.info->gap = gap;
             if (!conv) a.st->svd_capped = 1;
             if (kept < r && Gy[0] > 0.0) a.st->rank_drop = 1;
         }
+    }
+    // gap estimate sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr)),
+    // lambda_min(Gy_rr) = 1 / ||Ly^-1||_2^2 by power steps on Ly^-T Ly^-1; on
+    // the last workgroup, while the first writes the small outputs
+    if (wg == G - 1) {
+        double gap = -1.0;
+        if (live > r && w4 == 0) {
+            double v = l64 < r ? 1.0 : 0.0, lam = 0.0;
+            for (int s = 0; s < 8; ++s) {
+                red[l64] = v;
+                __builtin_amdgcn_wave_barrier();
+                double w = 0.0;
+                if (l64 < 16) {
+                    double m_[16], v_[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[k * XS + l64]; v_[k] = red[k]; }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) w = __builtin_fma(m_[k], v_[k], w);
+                }
+                __builtin_amdgcn_wave_barrier();
+                red[l64] = w;
+                __builtin_amdgcn_wave_barrier();
+                double u = 0.0;
+                if (l64 < 16) {
+                    double m_[16], v_[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[l64 * XS + k]; v_[k] = red[k]; }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) u = __builtin_fma(m_[k], v_[k], u);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const double nv = __builtin_sqrt(wave_sum_dpp(u * u));
+                const double vv = __builtin_sqrt(wave_sum_dpp(v * v));
+                lam = vv > 0.0 ? nv / vv : 0.0;
+                v = nv > 0.0 ? u / nv : 0.0;
+            }
+            gap = __builtin_sqrt(fmax(bx, 0.0) * lam);
+        }
+        if (tid == 0) a.info->gap = gap;
     }
     CPHASE(10);
 #ifdef IRCUR_PHASE_PROFILE
@@ -792,7 +777,7 @@ hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream
     if (dtype == 0) { fn = (const void*)csvd_kernel<double>; slot = 0; }
     if (dtype == 1) { fn = (const void*)csvd_kernel<float>; slot = 1; }
     if (dtype == 2) { fn = (const void*)csvd_kernel<bf16_t>; slot = 2; }
-    if (!fn || a.G < 1 || a.R > 16) return hipErrorInvalidValue;
+    if (!fn || a.G < 1 || a.R > 16 || a.xs < 1) return hipErrorInvalidValue;
     static bool attr_set[3] = {false, false, false};
     if (!attr_set[slot]) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -801,7 +786,7 @@ hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream
     }
     CsvdArgs b = a;
     void* args[] = {&b};
-    return hipLaunchKernel(fn, dim3(a.G), dim3(NT), args, lds_bytes, s);
+    return hipLaunchKernel(fn, dim3(a.G * a.xs), dim3(NT), args, lds_bytes, s);
 }
 
 }  // namespace ircur

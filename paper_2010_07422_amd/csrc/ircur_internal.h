@@ -197,6 +197,9 @@ struct CsvdArgs {
     SvdInfo* info;
     DevState* st;
     int32_t prof_slot;     // profile builds: phase timers of a repeated launch go to phase2
+    int32_t xs;            // workgroup stride: the grid has G * xs workgroups and those with
+                           // blockIdx % xs == 0 work (xs = number of XCDs: all on one XCD,
+                           // whose L2 then holds the exchanged data; dispatch is round robin)
 };
 
 struct FinArgs {
