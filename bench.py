@@ -44,7 +44,8 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
 # sources that define the kernel and its launch are the ones measured.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pass_kernel_n10000_r10_traffic.md")
 PASS_SOURCES = ("paper_2010_07422_amd/csrc/ircur_kernels.hip", "paper_2010_07422_amd/csrc/ircur_device.h",
-                "paper_2010_07422_amd/csrc/ircur_internal.h", "paper_2010_07422_amd/csrc/ircur_capi.hip")
+                "paper_2010_07422_amd/csrc/ircur_internal.h", "paper_2010_07422_amd/csrc/ircur_capi.hip",
+                "paper_2010_07422_amd/csrc/ircur_pass16.hip")
 
 
 def pass_source_hash():

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libircur.so")
-SOURCES = ["ircur_kernels.hip", "ircur_svd.hip", "ircur_csvd.hip", "ircur_export.hip", "ircur_alg2.hip", "ircur_unrolled.hip", "ircur_unrolled_api.hip",
+SOURCES = ["ircur_kernels.hip", "ircur_pass16.hip", "ircur_svd.hip", "ircur_csvd.hip", "ircur_export.hip", "ircur_alg2.hip", "ircur_unrolled.hip", "ircur_unrolled_api.hip",
            "ircur_capi.hip"]
 ARCH = os.environ.get("IRCUR_OFFLOAD_ARCH", "gfx950")
 
@@ -32,6 +32,7 @@ FLAGS = [
 # accumulation registers around every product in its loops).
 SRC_FLAGS = {
     "ircur_csvd.hip": ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form"],
+    "ircur_pass16.hip": ["-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form"],
 }
 
 

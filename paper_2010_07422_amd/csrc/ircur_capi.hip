@@ -178,6 +178,9 @@ struct ircur_ctx {
     bool csvd = false;              // core gather and SVD in one launch (ircur_csvd.hip)
     int Gc = 0;                     // its workgroups, ceil(sI / 16)
     int Xs = 1;                     // their stride in the grid (all on one XCD when it fits)
+    bool p16 = false;               // the matrix-core pass (with the one-launch SVD's operand tiles)
+    void* rowIt = nullptr;          // per-row data in operand-tile order, rows I and J
+    void* rowJt = nullptr;
     size_t csvd_lds = 0;
     double* Xr = nullptr;           // its exchange block (sJ16 x 16)
     int32_t* Icur = nullptr;        // index sets of an export (device)
@@ -289,7 +292,7 @@ void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
                     c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Xr, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
-                    c->info, c->hist};
+                    c->info, c->hist, c->rowIt, c->rowJt};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c->Ipin) (void)hipHostFree(c->Ipin);
@@ -369,13 +372,13 @@ PassArgs pass_args(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd) {
     PassArgs pa{};
     SideArgs& r0 = pa.side[0];
     r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
-    r0.rowdata = c->rowI; r0.Gm = c->GmI; r0.outmat = nullptr; r0.out = c->B[nxt];
+    r0.rowdata = c->rowI; r0.tiled = c->rowIt; r0.Gm = c->GmI; r0.outmat = nullptr; r0.out = c->B[nxt];
     r0.part = c->part_row; r0.nwg = c->nwg_row;
     const size_t fblk = pass_split_bytes(p.dtype, c->R) - 128 * sizeof(double);   // F sums per block
     r0.nsplit = c->ns_row; r0.pacc = c->pacc; r0.pzd = c->pzd; r0.cnt = c->pcnt;
     SideArgs& r1 = pa.side[1];
     r1.X = c->Dt; r1.ldX = c->ldDt; r1.rows = Jd; r1.s = p.sJ; r1.n = p.n1; r1.P = c->At[cur];
-    r1.rowdata = c->rowJ; r1.Gm = c->GmJ; r1.outmat = c->scaleJ; r1.out = c->At[nxt];
+    r1.rowdata = c->rowJ; r1.tiled = c->rowJt; r1.Gm = c->GmJ; r1.outmat = c->scaleJ; r1.out = c->At[nxt];
     r1.part = c->part_col; r1.nwg = c->nwg_col;
     const size_t nb0 = (size_t)c->nwg_row * c->ns_row;
     r1.nsplit = c->ns_col; r1.pacc = (char*)c->pacc + nb0 * fblk; r1.pzd = c->pzd + nb0 * 128;
@@ -426,6 +429,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
         ka.prevV = c->prevV; ka.Zp = c->Zp; ka.Gp = c->Gp; ka.Xr = c->Xr; ka.rp = c->rp;
         ka.W = c->W; ka.V = c->V; ka.sigma = c->sigma;
         ka.rowI = c->rowI; ka.rowJ = c->rowJ; ka.qs = row_stride(c->R, (int)c->fsz);
+        ka.rowIt = c->rowIt; ka.rowJt = c->rowJt;
         ka.GmI = c->GmI; ka.GmJ = c->GmJ; ka.scaleJ = c->scaleJ; ka.TAd = c->TAd;
         ka.info = c->info + k; ka.st = c->st;
         if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][1], s));
@@ -652,8 +656,12 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->esz = p.dtype == IRCUR_F64 ? 8 : (p.dtype == IRCUR_F32 ? 4 : 2);
     c->fsz = p.dtype == IRCUR_F64 ? 8 : 4;
     c->D = D_dev;
-    c->nwg_row = (int)((p.n2 + pass_cols(p.dtype) - 1) / pass_cols(p.dtype));
-    c->nwg_col = (int)((p.n1 + pass_cols(p.dtype) - 1) / pass_cols(p.dtype));
+    c->p16 = c->csvd && pass16_ok(p.dtype, c->R, std::max(p.sI, p.sJ));
+    {
+        const int pc = pass_cols(p.dtype, c->R, c->p16);
+        c->nwg_row = (int)((p.n2 + pc - 1) / pc);
+        c->nwg_col = (int)((p.n1 + pc - 1) / pc);
+    }
 
 #define TRY(x)                      \
     do {                            \
@@ -740,8 +748,14 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     TRY(dalloc(c, &c->nnz, 1));
     TRY(dalloc(c, &c->part_row, (size_t)2 * c->nwg_row));
     TRY(dalloc(c, &c->part_col, (size_t)2 * c->nwg_col));
-    c->ns_row = pass_nsplit(p.dtype, c->R, p.sI, c->nwg_row);
-    c->ns_col = pass_nsplit(p.dtype, c->R, p.sJ, c->nwg_col);
+    // (the matrix-core pass keeps every row of a column tile in one workgroup)
+    c->ns_row = c->p16 ? 1 : pass_nsplit(p.dtype, c->R, p.sI, c->nwg_row);
+    c->ns_col = c->p16 ? 1 : pass_nsplit(p.dtype, c->R, p.sJ, c->nwg_col);
+    if (c->p16) {
+        const size_t nbt = (size_t)(2 * ((c->R + 3) / 4) + 4) * 64 * c->fsz;
+        TRY(dalloc_bytes(c, &c->rowIt, (size_t)((p.sI + 15) / 16) * nbt));
+        TRY(dalloc_bytes(c, &c->rowJt, (size_t)((p.sJ + 15) / 16) * nbt));
+    }
     {
         const size_t nblk = (size_t)c->nwg_row * c->ns_row + (size_t)c->nwg_col * c->ns_col;
         TRY(dalloc_bytes(c, &c->pacc, nblk * (pass_split_bytes(p.dtype, c->R) - 128 * sizeof(double))));

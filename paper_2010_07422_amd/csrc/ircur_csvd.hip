@@ -682,23 +682,67 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         fput(a.rowI, base + 2 * R + c, Ab[ar * 16 + c] - Y[ar * 16 + c], fd);
         a.W[(int64_t)(a0 + ar) * R + c] = Wb[ar * 16 + c];
     }
-    // rows of this workgroup's slice: [B_k[:, J_b] | Q[b, :] | B_k[:, J_b] - Gamma' Q[b, :]^T]
+    // rows of this workgroup's slice: [B_k[:, J_b] | Q[b, :] | B_k[:, J_b] - Gamma' Q[b, :]^T],
+    // the last part formed first into Zs (no longer needed), zero past |J|
+    for (int e = tid; e < ntl * 256; e += NT) {
+        const int bl = e >> 4, c = e & 15;
+        const int b = 16 * t0 + bl;
+        double dl = 0.0;
+        if (b < sJ && c < R) {
+            double g_[16], x_[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) { g_[i] = Gam2[c * 16 + i]; x_[i] = X[b * XS + i]; }
+            double sg = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sg = __builtin_fma(g_[i], x_[i], sg);
+            dl = Bsl[e] - sg;
+        }
+        Zs[e] = dl;
+    }
+    __syncthreads();
     for (int e = tid; e < ntl * 16 * R; e += NT) {
         const int bl = e / R, c = e - bl * R;
         const int b = 16 * t0 + bl;
         if (b >= sJ) continue;
-        double g_[16], x_[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) { g_[i] = Gam2[c * 16 + i]; x_[i] = X[b * XS + i]; }
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) s = __builtin_fma(g_[i], x_[i], s);
         const int64_t base = (int64_t)b * a.qs;
-        const double bcj = Bsl[(bl >> 4) * 256 + (bl & 15) * 16 + c];
+        const double bcj = Bsl[bl * 16 + c];
         fput(a.rowJ, base + c, bcj, fd);
         fput(a.rowJ, base + R + c, X[b * XS + c], fd);
-        fput(a.rowJ, base + 2 * R + c, bcj - s, fd);
+        fput(a.rowJ, base + 2 * R + c, Zs[bl * 16 + c], fd);
         a.V[(int64_t)b * R + c] = X[b * XS + c];
+    }
+    // the same per-row data in the operand-tile order of the matrix-core pass:
+    // per 16-row tile, ceil(R/4) blocks of the A operand of the products with
+    // the factor (lane l: row l % 16, factor index 4 ks + l / 16), as many of
+    // the Delta part, then four blocks of the projection part (lane l: row of
+    // accumulator register v in the pass's layout, factor index l % 16)
+    if (a.rowIt) {
+        const int KRt = (R + 3) / 4, NBt = (2 * KRt + 4) * 64;
+        for (int e = tid; e < (1 + ntl) * NBt; e += NT) {
+            const int q = e / NBt - 1, f = e - (q + 1) * NBt, kind = f >> 6, l = f & 63;
+            double v = 0.0;
+            int row, c;
+            if (kind < 2 * KRt) {
+                row = l & 15;
+                c = 4 * (kind < KRt ? kind : kind - KRt) + (l >> 4);
+            } else {
+                const int vv = kind - 2 * KRt;
+                row = fd == 0 ? (l >> 4) + 4 * vv : 4 * (l >> 4) + vv;
+                c = l & 15;
+            }
+            if (q < 0) {                             // this workgroup's row tile of I
+                if (row < nb && c < R)
+                    v = kind < KRt ? Ab[row * 16 + c]
+                                   : (kind < 2 * KRt ? Ab[row * 16 + c] - Y[row * 16 + c] : Wb[row * 16 + c]);
+                fput(a.rowIt, (int64_t)wg * NBt + f, v, fd);
+            } else {                                 // slice tile t0 + q of J
+                const int b = 16 * (t0 + q) + row;
+                if (b < sJ && c < R)
+                    v = kind < KRt ? Bsl[q * 256 + row * 16 + c]
+                                   : (kind < 2 * KRt ? Zs[q * 256 + row * 16 + c] : X[b * XS + c]);
+                fput(a.rowJt, (int64_t)(t0 + q) * NBt + f, v, fd);
+            }
+        }
     }
     if (wg == 0) {
         for (int e = tid; e < R * R; e += NT) {

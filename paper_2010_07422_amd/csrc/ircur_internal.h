@@ -26,8 +26,19 @@ inline int row_stride(int R, int fsz) { return ((3 * R * fsz + 15) / 16) * (16 /
 // column tile.
 constexpr int kPassSplitRows = 128;
 constexpr int kPassMaxSplit = 64;
-// Output columns of one pass column tile (64 lanes x the columns per lane).
-int pass_cols(int dtype);
+// Output columns of one pass column tile: 16 for the matrix-core pass
+// (padded ranks up to kPass16MaxRank), 64 lanes x the columns per lane above.
+constexpr int kPass16MaxRank = 16;
+constexpr int kPass16MinRank = 8;
+constexpr int kPass16MaxRows = 1024;
+// The matrix-core pass applies: kPass16MinRank <= R <= kPass16MaxRank (below,
+// the 16-row operand of the projection product is mostly padding and the
+// vector pass moves fewer bytes), at most kPass16MaxRows sampled rows per side
+// (their indices are staged in LDS), and the per-row data written in
+// operand-tile order (by the one-launch SVD).
+bool pass16_ok(int dtype, int R, int smax);
+int pass_cols(int dtype, int R, bool matrix_core);
+size_t pass16_lds_bytes(int dtype, int R, int s);
 
 inline int pad_rank(int r) {
     for (int v : kRanks) if (v >= r) return v;
@@ -71,6 +82,8 @@ struct SideArgs {
     int64_t n;             // row length (n2 or n1)
     const void* P;         // B_k (side 0) or A_k^T (side 1): R x n, row stride n
     const void* rowdata;   // s x QS (QS = row_stride): [gathered factor | projection | Delta]
+    const void* tiled;     // the same in operand-tile order for the matrix-core pass
+                           // (ceil(s/16) blocks of (2 ceil(R/4) + 4) x 64), or nullptr
     const void* Gm;        // R x R: Gamma (side 0) or Gamma'^T (side 1)
     const void* outmat;    // R x R map applied to the output row (nullptr: identity)
     void* out;             // new factor, R x n, row stride n
@@ -192,6 +205,8 @@ struct CsvdArgs {
     void* rowI;            // sI x qs (factor dtype)
     void* rowJ;            // sJ x qs
     int32_t qs;
+    void* rowIt;           // the per-row data in operand-tile order (see SideArgs::tiled), or nullptr
+    void* rowJt;
     void* GmI; void* GmJ; void* scaleJ;
     double* TAd;
     SvdInfo* info;
@@ -312,6 +327,7 @@ hipError_t launch_svd_batch(const SvdArgs* arr_dev, int nb, int G, int P, size_t
 hipError_t launch_svdl(const SvdArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_svdl_batch(const SvdArgs* arr_dev, int nb, int G, size_t lds_bytes, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s);
+hipError_t launch_pass16(const PassArgs& a, int dtype, int R, hipStream_t s);
 // Row blocks per column tile for a pass side with s rows (1: no split), and
 // the partial-sum bytes per (tile, block) that a split needs.
 int pass_nsplit(int dtype, int R, int s, int tiles);

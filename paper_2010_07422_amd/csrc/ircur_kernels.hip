@@ -198,6 +198,7 @@ hipError_t launch_core(const CoreArgs& a, int dtype, int R, hipStream_t s) {
 }
 
 hipError_t launch_pass(const PassArgs& a, int dtype, int R, hipStream_t s) {
+    if (a.side[0].tiled && a.side[1].tiled) return launch_pass16(a, dtype, R, s);
     if (dtype == 0) { IRCUR_RANK_SWITCH(pass_r, double, double, R, a, s) }
     if (dtype == 1) { IRCUR_RANK_SWITCH(pass_r, float, float, R, a, s) }
     if (dtype == 2) { IRCUR_RANK_SWITCH(pass_r, bf16_t, float, R, a, s) }
@@ -220,14 +221,16 @@ int pass_nsplit(int dtype, int R, int s, int tiles) {
     return 1;
 }
 
-int pass_cols(int dtype) {
+int pass_cols(int dtype, int R, bool matrix_core) {
+    (void)R;
+    if (matrix_core) return 32;
     return 64 * (dtype == 2 ? ColsPerLane<bf16_t>::value : (dtype == 1 ? ColsPerLane<float>::value
                                                                        : ColsPerLane<double>::value));
 }
 
 size_t pass_split_bytes(int dtype, int R) {
     const size_t f = dtype == 0 ? sizeof(double) : sizeof(float);
-    const size_t V = pass_cols(dtype) / 64;
+    const size_t V = pass_cols(dtype, R, false) / 64;
     return (size_t)R * V * 64 * f + 128 * sizeof(double);
 }
 
