@@ -251,9 +251,9 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     int* spare = Il + 16;                 // 16
     (void)spare;
 
-    // ---- load: the core kernel's M block (row-tiled layout), A_k[I_blk, :], B_k[:, J] ----
-    // (one round trip; the core kernel gathered and thresholded the block on
-    // every compute unit)
+    // ---- load: the core launch's M block (row-tiled layout), A_k[I_blk, :] and the
+    // orthonormal warm start it formed (one round trip; the core launch gathered
+    // and thresholded the block on every compute unit) ----
     {
         const double* __restrict__ src = a.MA + (size_t)wg * KS * 64;   // row tile wg: KS blocks of 64
         constexpr int UL = 32;            // doubles per thread (|J| <= 512)
@@ -261,10 +261,9 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #pragma unroll
         for (int u = 0; u < UL; ++u) mv[u] = src[min(tid + NT * u, KS * 64 - 1)];   // (clamped: no branch per load)
         const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
-        // B_k[c, J_b] (compact, 16 x sJ16) into X[b][c]
-        double bv[18];
+        double wv[18];
 #pragma unroll
-        for (int u = 0; u < 18; ++u) bv[u] = a.Bsc[min(tid + NT * u, 16 * sJ16 - 1)];
+        for (int u = 0; u < 18; ++u) wv[u] = a.WQ[min(tid + NT * u, 16 * sJ16 - 1)];
         // the run state is read with the loads above in flight; a stopped run
         // returns before it writes anything
         if (a.st->stop) return;
@@ -279,12 +278,14 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         Ab[tid] = (tid >> 4) < nb ? av : 0.0;
 #pragma unroll
         for (int u = 0; u < 18; ++u) {
-            const int e = tid + NT * u, c = e / sJ16, b = e - c * sJ16;
-            if (c < 16) X[b * XS + c] = bv[u];
+            const int e = tid + NT * u;
+            if (e < 16 * sJ16) X[(e >> 4) * XS + (e & 15)] = wv[u];
         }
-        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) {      // |J| > 288: the rest
-            const int c = e / sJ16, b = e - c * sJ16;
-            X[b * XS + c] = a.Bsc[e];
+        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) X[(e >> 4) * XS + (e & 15)] = a.WQ[e];   // |J| > 288
+        // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
+        for (int e = tid; e < ntl * 256; e += NT) {
+            const int b = 16 * t0 + (e >> 4), c = e & 15;
+            Bsl[e] = a.Bsc[(size_t)c * sJ16 + b];
         }
     }
     __syncthreads();
@@ -292,29 +293,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
     const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
     const int min_passes = 1;
-    // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
-    for (int e = tid; e < ntl * 256; e += NT) {
-        const int b = 16 * t0 + (e >> 4), c = e & 15;
-        Bsl[e] = X[b * XS + c];
-    }
-    __syncthreads();
-    // warm start: IRCUR-R keeps B_k[:, J]^T as the wanted columns
-    for (int e = tid; e < sJ16 * 16; e += NT) {
-        const int b = e >> 4, c = e & 15;
-        double v = 0.0;
-        if (b < sJ && c < live) {
-            if (a.warm == 2) v = c < r ? X[b * XS + c] : rnd_unit(a.salt, (uint64_t)e);
-            else v = a.warm == 1 ? a.prevV[e] : rnd_unit(a.salt, (uint64_t)e);
-        }
-        X[b * XS + c] = v;
-    }
-    __syncthreads();
     CPHASE(0);
-    {
-        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, a.warm == 1 ? 1 : min_passes, Gs, LiT, dead, cst,
-                                scr, a.salt + 17);
-        QADD(q);
-    }
     CPHASE(1);
 
     // ---- subspace iteration -------------------------------------------------
@@ -813,6 +792,110 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         (void)c_start; (void)r_start;
     }
 #endif
+}
+
+// ---- warm start (one more workgroup of the core launch) ----------------------
+// X0 (|J| x 16): IRCUR-R keeps B_k[:, J]^T as the wanted columns, the extra
+// ones (and every column of a cold start) pseudo-random; with the index set of
+// the previous iteration the previous basis.  Orthonormalised by Cholesky QR
+// (as in the SVD's sweeps) into WQ while the other workgroups gather the core.
+size_t warm_lds_bytes(int sJ) {
+    const size_t sJ16 = ((size_t)sJ + 15) / 16 * 16;
+    return (17 * sJ16 + 2 * 16 * XS + 16 + 4 * 256 + 32) * sizeof(double) + 64 * sizeof(int);
+}
+
+template <typename F>
+__device__ void warm_body(const CoreArgs& a) {
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+#ifdef IRCUR_PHASE_PROFILE
+    const uint64_t w0_ = __builtin_amdgcn_s_memrealtime();
+#endif
+    const int sJ = a.sJ, sJ16 = ((sJ + 15) / 16) * 16, r = a.r, live = min(16, sJ);
+    double* X = smem;
+    double* Gs = X + sJ16 * XS;
+    double* LiT = Gs + 16 * XS;
+    double* cst = LiT + 16 * XS;
+    double* scr = cst + 16;               // 4 x 256 + 32
+    int* dead = (int*)(scr + 4 * 256 + 32);
+    const F* __restrict__ B = (const F*)a.B;
+    // the run state first (its loads overlap the ones below)
+    const int32_t kd = a.st->k_done;
+    const double el = a.st->e_last;
+    const int tot = 16 * sJ16;
+    for (int e0 = tid; e0 < tot; e0 += NT * 18) {
+        // indices, then factor entries / previous basis, 18 per thread in flight
+        int jb[18];
+#pragma unroll
+        for (int u = 0; u < 18; ++u) jb[u] = a.J[min((e0 + NT * u) >> 4, sJ - 1)];
+        double v[18];
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            const int e = min(e0 + NT * u, tot - 1), c = e & 15;
+            if (a.warm == 2) v[u] = (double)B[(int64_t)(c < r ? c : 0) * a.n2 + jb[u]];
+            else v[u] = a.warm == 1 ? a.prevV[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 18; ++u) {
+            const int e = e0 + NT * u;
+            if (e >= tot) continue;
+            const int b = e >> 4, c = e & 15;
+            double x = 0.0;
+            if (b < sJ && c < live) {
+                if (a.warm == 2) x = c < r ? v[u] : rnd_unit(a.salt, (uint64_t)e);
+                else x = a.warm == 1 ? v[u] : rnd_unit(a.salt, (uint64_t)e);
+            }
+            X[b * XS + c] = x;
+        }
+    }
+    __syncthreads();
+    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (kd > 0 ? el : 1.0)) : a.tol;
+    const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
+#ifdef IRCUR_PHASE_PROFILE
+    const uint64_t w1_ = __builtin_amdgcn_s_memrealtime();
+#endif
+    (void)cholqr(X, sJ16, sJ, live, kappa2_one, 1, Gs, LiT, dead, cst, scr, a.salt + 17);
+    for (int e = tid; e < tot; e += NT) a.WQ[e] = X[(e >> 4) * XS + (e & 15)];
+#ifdef IRCUR_PHASE_PROFILE
+    if (tid == 0) {
+        const uint64_t w2_ = __builtin_amdgcn_s_memrealtime();
+        a.st->phase[11] += w1_ - w0_;
+        a.st->phase[12] += w2_ - w1_;
+    }
+#endif
+}
+
+template <typename T, typename F, int R>
+__global__ __launch_bounds__(256) void core_warm_kernel(CoreArgs a) {
+    if (a.st->stop) return;
+    // the warm start takes the first workgroup (dispatched first: it is the
+    // longest), the core gather the others
+    if (blockIdx.x > 0) core_body<T, F, R>(a, (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x);
+    else warm_body<F>(a);
+}
+
+template <typename T, typename F, int R>
+static hipError_t core_warm_r(const CoreArgs& a, hipStream_t s) {
+    const int64_t total = (int64_t)a.sI * a.sJ;
+    const unsigned grid = (unsigned)((total + 255) / 256) + 1;
+    const size_t lds = warm_lds_bytes(a.sJ);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)core_warm_kernel<T, F, R>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    core_warm_kernel<T, F, R><<<grid, 256, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_core_warm(const CoreArgs& a, int dtype, int R, hipStream_t s) {
+    if (R > 16) return hipErrorInvalidValue;
+    if (dtype == 0) { IRCUR_RANK_SWITCH(core_warm_r, double, double, R, a, s) }
+    if (dtype == 1) { IRCUR_RANK_SWITCH(core_warm_r, float, float, R, a, s) }
+    if (dtype == 2) { IRCUR_RANK_SWITCH(core_warm_r, bf16_t, float, R, a, s) }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s) {

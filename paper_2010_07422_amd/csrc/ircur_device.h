@@ -349,6 +349,39 @@ __device__ __forceinline__ void side_body(const SideArgs& S, int wg, int blk, do
 
 
 
+// One element of the core M = [D - S_{k+1}]_{I,J} (eq. (4), (5)) at flat
+// index idx = a * |J| + b, in every layout the SVD reads (see CoreArgs), and
+// the compact factor copies.  Shared by the core kernel and the core launch
+// of the one-launch SVD.
+template <typename T, typename F, int R>
+__device__ __forceinline__ void core_body(const CoreArgs& a, int64_t idx) {
+    if (idx >= (int64_t)a.sI * a.sJ) return;
+    const int ai = (int)(idx / a.sJ), bj = (int)(idx - (int64_t)ai * a.sJ);
+    const int64_t i = a.I[ai], j = a.J[bj];
+    const T* __restrict__ D = (const T*)a.D;
+    const F* __restrict__ At = (const F*)a.At;
+    const F* __restrict__ B = (const F*)a.B;
+    const F d = ld<T, F>(D + i * a.ldD + j);
+    F dot = F(0);
+#pragma unroll
+    for (int c = 0; c < R; ++c) dot = fmaT(At[c * a.n1 + i], B[c * a.n2 + j], dot);
+    bool o;
+    const F v = entry_value<F>(d, dot, a.zeta, a.zeta_f, &o);
+    const double mv = (double)v;
+    a.M[idx] = mv;
+    const int sJ16 = ((a.sJ + 15) / 16) * 16, sI16 = ((a.sI + 15) / 16) * 16;
+    a.MA[((size_t)(ai >> 4) * (sJ16 >> 2) + (bj >> 2)) * 64 + ((bj & 3) << 4) + (ai & 15)] = mv;
+    if (a.MB) a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
+    if (a.Abc && bj == 0) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) a.Abc[(size_t)ai * 16 + c] = (double)At[c * a.n1 + i];
+    }
+    if (a.Bsc && ai == 0) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) a.Bsc[(size_t)c * sJ16 + bj] = (double)B[c * a.n2 + j];
+    }
+}
+
 #define IRCUR_RANK_SWITCH(FN, T, F, R, ...)                     \
     switch (R) {                                                \
         case 1: return FN<T, F, 1>(__VA_ARGS__);                \

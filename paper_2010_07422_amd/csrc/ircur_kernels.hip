@@ -73,32 +73,7 @@ template <typename T, typename F, int R>
 __global__ __launch_bounds__(256) void core_kernel(CoreArgs a) {
     if (a.st->stop) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.st->bar_ctr = 0u;  // for the SVD's grid barrier
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)a.sI * a.sJ) return;
-    const int ai = (int)(idx / a.sJ), bj = (int)(idx - (int64_t)ai * a.sJ);
-    const int64_t i = a.I[ai], j = a.J[bj];
-    const T* __restrict__ D = (const T*)a.D;
-    const F* __restrict__ At = (const F*)a.At;
-    const F* __restrict__ B = (const F*)a.B;
-    const F d = ld<T, F>(D + i * a.ldD + j);
-    F dot = F(0);
-#pragma unroll
-    for (int c = 0; c < R; ++c) dot = fmaT(At[c * a.n1 + i], B[c * a.n2 + j], dot);
-    bool o;
-    const F v = entry_value<F>(d, dot, a.zeta, a.zeta_f, &o);
-    const double mv = (double)v;
-    a.M[idx] = mv;
-    const int sJ16 = ((a.sJ + 15) / 16) * 16, sI16 = ((a.sI + 15) / 16) * 16;
-    a.MA[((size_t)(ai >> 4) * (sJ16 >> 2) + (bj >> 2)) * 64 + ((bj & 3) << 4) + (ai & 15)] = mv;
-    if (a.MB) a.MB[((size_t)(bj >> 4) * (sI16 >> 2) + (ai >> 2)) * 64 + ((ai & 3) << 4) + (bj & 15)] = mv;
-    if (a.Abc && bj == 0) {
-#pragma unroll
-        for (int c = 0; c < R; ++c) a.Abc[(size_t)ai * 16 + c] = (double)At[c * a.n1 + i];
-    }
-    if (a.Bsc && ai == 0) {
-#pragma unroll
-        for (int c = 0; c < R; ++c) a.Bsc[(size_t)c * sJ16 + bj] = (double)B[c * a.n2 + j];
-    }
+    core_body<T, F, R>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // ----------------------------------------------------------------- pass ---
