@@ -86,6 +86,14 @@ typedef struct {
                             iteration before, e_0 = 1)                              */
     int32_t svd_max_it;  /* subspace-iteration cap of the top-r SVD; 0: default 64   */
     int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default       */
+    const double* zeta_sched; /* optional host array of max_iter thresholds (Algorithm
+                            1, Phase I: any decreasing schedule zeta_{k+1}):
+                            iteration k (0-based) thresholds with zeta_sched[k] in
+                            place of gamma^k zeta_0; NULL: the geometric schedule.
+                            Copied by ircur_init (the caller keeps ownership);
+                            every entry finite and >= 0, else IRCUR_ERR_ARG.
+                            Past the last iteration (ircur_sparse_full with
+                            zeta < 0 after max_iter iterations) the last entry. */
 } ircur_params;
 
 /* Fill *p with defaults (gamma 0.7, eps 1e-5, max_iter 100, resample 1,
@@ -229,6 +237,12 @@ int ircur_sparse_full(ircur_ctx* ctx, double zeta, void* S_dev, int64_t ldS,
 int ircur_get_state(ircur_ctx* ctx, void* buf, size_t* bytes);
 int ircur_set_state(ircur_ctx* ctx, const void* buf, size_t bytes);
 
+/* ---- Measurement entry points --------------------------------------------
+ * The calls from here to ircur_time_sparse, and ircur_get_phase_profile(2)
+ * below, are tooling for benchmarks and profiles: they compute nothing of
+ * Algorithm 1 and leave the run's state as it was.  A solver needs none of
+ * them. */
+
 /*
  * Per-kernel timing with HIP events on the context's stream (for the
  * benchmark).  When enabled, every iteration records events around its
@@ -296,9 +310,9 @@ int ircur_sample(uint64_t seed, int64_t t, int64_t n1, int64_t n2, int32_t sI,
                  int32_t sJ, int32_t* I_host, int32_t* J_host);
 
 /*
- * Accumulated phase times (microseconds) of the SVD kernel's first
- * workgroup, 16 slots, for builds compiled with IRCUR_PHASE_PROFILE (zeros
- * otherwise).  Synchronises.
+ * (Tooling.)  Accumulated phase times (microseconds) of the SVD kernel's
+ * first workgroup, 16 slots, for builds compiled with IRCUR_PHASE_PROFILE
+ * (zeros otherwise).  Synchronises.
  */
 int ircur_get_phase_profile(ircur_ctx* ctx, double* us16);
 /* Profile builds: the same timers for a second launch of the one-launch SVD

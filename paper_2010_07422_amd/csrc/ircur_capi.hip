@@ -184,6 +184,7 @@ struct ircur_ctx {
     size_t csvd_lds = 0;
     double* Xr = nullptr;           // its exchange block (sJ16 x 16)
     double* WQ = nullptr;           // its warm start, formed by the core launch (sJ16 x 16)
+    std::vector<double> zsched;     // the caller's threshold schedule (empty: geometric)
     int32_t* Icur = nullptr;        // index sets of an export (device)
     int32_t* Jcur = nullptr;
     unsigned long long* nnz = nullptr;
@@ -263,6 +264,9 @@ int validate(const ircur_params* p, const void* D, const void* Dt, int64_t ldDt)
         (p->svd_block < p->r || p->svd_block > 32 || p->svd_block > p->sI || p->svd_block > p->sJ))
         return IRCUR_ERR_ARG;
     if (Dt && ldDt < p->n1) return IRCUR_ERR_ARG;
+    if (p->zeta_sched)
+        for (int32_t k = 0; k < p->max_iter; ++k)
+            if (!(p->zeta_sched[k] >= 0.0) || std::isinf(p->zeta_sched[k])) return IRCUR_ERR_ARG;
     return IRCUR_OK;
 }
 
@@ -309,7 +313,11 @@ void free_all(ircur_ctx* c) {
     }
 }
 
-double zeta_at(const ircur_params& p, int k) { return p.zeta0 * std::pow(p.gamma, (double)k); }
+// zeta_{k+1} of Algorithm 1, Phase I: the caller's schedule, else gamma^k zeta_0.
+double zeta_at(const ircur_ctx* c, int k) {
+    if (!c->zsched.empty()) return c->zsched[std::min<size_t>((size_t)std::max(k, 0), c->zsched.size() - 1)];
+    return c->p.zeta0 * std::pow(c->p.gamma, (double)k);
+}
 
 // Reset device state, factors and history to L_0 = 0, k = 0.
 int reset_state(ircur_ctx* c) {
@@ -369,7 +377,7 @@ int status_after(ircur_ctx* c) {
 PassArgs pass_args(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd) {
     const ircur_params& p = c->p;
     const int cur = k & 1, nxt = cur ^ 1;
-    const double zeta = zeta_at(p, k);
+    const double zeta = zeta_at(c, k);
     PassArgs pa{};
     SideArgs& r0 = pa.side[0];
     r0.X = c->D; r0.ldX = p.ldD; r0.rows = Id; r0.s = p.sI; r0.n = p.n2; r0.P = c->B[cur];
@@ -401,7 +409,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     }
     const ircur_params& p = c->p;
     const int cur = k & 1, nxt = cur ^ 1;
-    const double zeta = zeta_at(p, k);
+    const double zeta = zeta_at(c, k);
     const float zf = round_down_float(zeta);
     hipStream_t s = c->stream;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][0], s));
@@ -605,6 +613,8 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     ircur_ctx* c = new (std::nothrow) ircur_ctx();
     if (!c) return IRCUR_ERR_ALLOC;
     c->p = *pin;
+    if (pin->zeta_sched) c->zsched.assign(pin->zeta_sched, pin->zeta_sched + pin->max_iter);
+    c->p.zeta_sched = nullptr;               // (the copy above is the context's)
     const ircur_params& p = c->p;
     c->R = pad_rank(p.r);
     // SVD: tile width P >= R; workgroups G the fewest of 8, 16, 32 whose LDS
@@ -972,7 +982,7 @@ int ircur_get_cur(ircur_ctx* c, void* C_dev, void* Upinv_dev, void* R_dev, void*
     a.D = c->D; a.ldD = p.ldD; a.Dt = c->Dt; a.ldDt = c->ldDt;
     a.I = c->Icur; a.J = c->Jcur; a.sI = p.sI; a.sJ = p.sJ; a.n1 = p.n1; a.n2 = p.n2;
     a.At = c->At[prev]; a.B = c->B[prev];
-    a.zeta = zeta_at(p, it); a.zeta_f = round_down_float(a.zeta);
+    a.zeta = zeta_at(c, it); a.zeta_f = round_down_float(a.zeta);
     a.Rout = R_dev; a.SI = SI_dev; a.Cout = C_dev; a.SJ = SJ_dev;
     if (R_dev || SI_dev || C_dev || SJ_dev) HIPCHK(c, launch_cur(a, p.dtype, c->R, c->stream));
     if (Upinv_dev)
@@ -1034,7 +1044,7 @@ static SparseArgs sparse_args(const ircur_ctx* c, double zeta, void* S_dev, int6
     SparseArgs a{};
     a.D = c->D; a.ldD = p.ldD; a.n1 = p.n1; a.n2 = p.n2;
     a.At = c->At[cur]; a.B = c->B[cur];
-    a.zeta = zeta < 0.0 ? zeta_at(p, c->k) : zeta;
+    a.zeta = zeta < 0.0 ? zeta_at(c, c->k) : zeta;
     a.zeta_f = round_down_float(a.zeta);
     a.S = S_dev; a.ldS = ldS;
     return a;

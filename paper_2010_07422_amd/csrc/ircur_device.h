@@ -70,16 +70,18 @@ __device__ __forceinline__ F gate_value(F x, F zeta, F tauz) {
     return F(1) / (F(1) + exp_t(-(ax - zeta) / tauz));
 }
 
-// One workgroup: 64 V consecutive outputs (V per lane: 2 for BF16 so that a
-// wave reads 256-byte row segments, 1 otherwise) x all s gathered rows.  The
-// NW waves split the rows into contiguous chunks; each keeps U row loads in
-// flight.  The per-wave partial sums are combined by a fixed binary tree in
-// LDS (the result does not depend on scheduling).  The per-row data
-// (gathered factor row, projection row, Delta row; QS elements per row,
-// 16-byte aligned) is wave-uniform: the workgroup stages it in LDS with
-// batched 16-byte loads (all rows at once unless they exceed the stage budget)
-// and reads it back as broadcast loads.  The index arrays carry kIndexPad
-// valid trailing entries, so a group may read past the end of a wave's rows.
+// The vector pass (padded ranks below 8 or above 16, and runs whose SVD takes
+// several launches; ircur_pass16.hip has the matrix-core one).  One
+// workgroup: 64 consecutive outputs (one column per lane) x a block of the s
+// gathered rows (row split: the blocks of a column tile meet through a ticket,
+// see side_body).  The NW waves split the block's rows into contiguous
+// chunks; each keeps U row loads in flight.  The per-wave partial sums are
+// combined by a fixed binary tree in LDS (the result does not depend on
+// scheduling).  The per-row data (gathered factor row, projection row, Delta
+// row; QS elements per row, 16-byte aligned) is wave-uniform: each wave reads
+// it through the scalar cache into SGPRs, the FMAs' uniform operand.  The
+// index arrays carry kIndexPad valid trailing entries, so a group may read
+// past the end of a wave's rows.
 // Rows in flight per wave (the next group is loaded while the current one is
 // processed), columns per lane and waves per workgroup, by storage type.
 // (Measured on MI355X at n = 10^4: FP64 is fastest with 8 waves, BF16 and

@@ -29,6 +29,7 @@ class Params(ctypes.Structure):
         ("zeta0", ctypes.c_double), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
         ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("svd_tol", ctypes.c_double), ("svd_max_it", ctypes.c_int32), ("svd_block", ctypes.c_int32),
+        ("zeta_sched", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -158,7 +159,7 @@ class IRCUR:
 
     def __init__(self, D, r, sI, sJ, zeta0, gamma=0.7, eps=1e-5, max_iter=100, seed=0,
                  resample=True, err_mode=0, Dt=None, svd_tol=0.0, svd_max_it=0,
-                 svd_block=0, stream=None):
+                 svd_block=0, stream=None, zeta_sched=None):
         import torch
         if not (isinstance(D, torch.Tensor) and D.is_cuda and D.dim() == 2 and D.stride(1) == 1):
             raise ValueError("D must be a 2-D CUDA tensor with unit column stride")
@@ -178,6 +179,13 @@ class IRCUR:
         p.max_iter = max_iter
         p.seed = seed
         p.svd_tol, p.svd_max_it, p.svd_block = float(svd_tol), svd_max_it, svd_block
+        sched = None
+        if zeta_sched is not None:
+            z = [float(v) for v in zeta_sched]
+            if len(z) < max_iter:
+                raise ValueError("zeta_sched needs max_iter entries")
+            sched = (ctypes.c_double * max_iter)(*z[:max_iter])
+            p.zeta_sched = ctypes.cast(sched, ctypes.POINTER(ctypes.c_double))
         self.p = p
         self.stream = stream
         h = ctypes.c_void_p()

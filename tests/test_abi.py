@@ -74,6 +74,17 @@ def test_init_rejects_invalid_parameters(field, value):
     assert not h.value   # *out set to NULL on error
 
 
+@pytest.mark.parametrize("bad", [float("nan"), -1.0, float("inf")])
+def test_init_rejects_invalid_threshold_schedule(bad):
+    p = _valid()
+    p.max_iter = 4
+    sched = (ctypes.c_double * 4)(1.0, 0.5, bad, 0.1)
+    p.zeta_sched = ctypes.cast(sched, ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p(123)
+    rc = B.lib().ircur_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(0x1000), None, 0, None)
+    assert rc == B.ERR_ARG and not h.value
+
+
 def test_init_rejects_null_pointers_and_bad_transpose_stride():
     p = _valid()
     h = ctypes.c_void_p()

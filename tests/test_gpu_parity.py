@@ -84,3 +84,32 @@ def test_run_planted_n1000_r5_f64_matches_oracle():
     h = np.array(ctx.history())
     assert np.allclose(h, ref.e_hist, rtol=1e-5, atol=0)
     ctx.close()
+
+
+def test_caller_threshold_schedule_matches_oracle():
+    """Algorithm 1, Phase I with a caller-given schedule zeta_{k+1} (not the
+    geometric one): a slower, uneven decay over 12 IRCUR-R iterations, FP64,
+    against oracle.ircur(zeta_sched=...) on the same D and index sets."""
+    torch = require_gpu()
+    n1, n2, r, s1, s2 = 700, 650, 4, 60, 55
+    p = synth.planted(n1, n2, r, 0.1, seed=77)
+    K = 12
+    sched = [p.Lmax * 0.85 ** k * (1.0 + 0.25 * np.cos(1.7 * k)) for k in range(K)]
+    ref = O.ircur(p.D, r, s1, s2, p.Lmax, 0.7, 0.0, K, seed=3, resample=True, zeta_sched=sched)
+    print("case zeta schedule n1=700 n2=650 r=4, 12 iterations", flush=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float64, r, s1, s2, p.Lmax, eps=0.0, max_iter=K, seed=3,
+                   resample=True, zeta_sched=sched)
+    it, e, rc = ctx.solve()
+    assert it == K
+    I, J = ctx.sets()
+    assert np.array_equal(I, ref.I) and np.array_equal(J, ref.J)
+    A, B = factors_np(ctx)
+    d = O.factored_rel_diff(A, B, ref.A, ref.B)
+    h = np.array(ctx.history())
+    print("rel diff vs oracle", d, "e", h[-1], ref.e_hist[-1], flush=True)
+    assert d <= 1e-10
+    assert np.all(np.abs(h - ref.e_hist) <= 1e-9 * np.array(ref.e_hist) + 1e-14)
+    # the geometric schedule of the same zeta_0 and gamma takes another path
+    ref_g = O.ircur(p.D, r, s1, s2, p.Lmax, 0.7, 0.0, K, seed=3, resample=True)
+    assert O.factored_rel_diff(A, B, ref_g.A, ref_g.B) > 1e-8 or not np.allclose(h, ref_g.e_hist)
+    ctx.close()
