@@ -84,8 +84,12 @@ typedef struct {
                             (1e-13 for F64, 1e-9 for F32; for BF16
                             max(1e-7, 1e-2 e_k), e_k the stopping residual of the
                             iteration before, e_0 = 1)                              */
-    int32_t svd_max_it;  /* subspace-iteration cap of the top-r SVD; 0: default 64   */
-    int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default       */
+    int32_t svd_max_it;  /* cap on the products with M^T M of one top-r SVD; 0: the
+                            default, 256 in the one-launch SVD (r <= 16), 64
+                            subspace iterations in the general one              */
+    int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default (16
+                            for r <= 16); a value other than 16 selects the
+                            general multi-launch SVD                            */
     const double* zeta_sched; /* optional host array of max_iter thresholds (Algorithm
                             1, Phase I: any decreasing schedule zeta_{k+1}):
                             iteration k (0-based) thresholds with zeta_sched[k] in

@@ -652,7 +652,9 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
         const int gc = (p.sI + 15) / 16;
-        if (c->R <= 16 && gc <= ncu && p.sJ <= 512 && csvd_lds_bytes(p.sJ, gc) <= 160 * 1024) {
+        // (a caller-chosen subspace width other than 16 takes the general SVD)
+        if (c->R <= 16 && gc <= ncu && p.sJ <= 512 && (p.svd_block == 0 || p.svd_block == 16) &&
+            csvd_lds_bytes(p.sJ, gc) <= 160 * 1024) {
             c->csvd = true;
             c->Gc = gc;
             c->csvd_lds = csvd_lds_bytes(p.sJ, gc);

@@ -88,7 +88,7 @@ struct SideArgs {
     const void* outmat;    // R x R map applied to the output row (nullptr: identity)
     void* out;             // new factor, R x n, row stride n
     double* part;          // 2 doubles per column tile: (residual, ||D_side||^2)
-    int32_t nwg;           // column tiles (64 V columns each)
+    int32_t nwg;           // column tiles (64 columns in the vector pass, 32 in the matrix-core one)
     // row split: nsplit workgroups per column tile, each over a block of
     // ceil(s / nsplit) rows; their partial sums meet in pacc/pzd and the last
     // workgroup of the tile to finish (ticket in cnt) adds them in block order

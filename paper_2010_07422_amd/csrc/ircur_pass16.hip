@@ -16,8 +16,9 @@
 // A workgroup owns 32 columns (two column tiles) and every sampled row, so no
 // partial sums leave it: each of its four waves takes one column tile and
 // every other 16-row tile, a few tiles at a time with all their operands
-// requested before the first product (the sampled row indices are staged in
-// LDS first).  On one tile, the
+// requested before the first product (all nine of its tiles at once with 32-bit
+// arithmetic and at most 288 sampled rows; the sampled row indices are staged
+// in LDS first).  On one tile, the
 // 16 x 16 block of x is the accumulator of R-deep products q P
 // (v_mfma_*_16x16x4); the thresholded block stays in those registers and is
 // the B operand of the products w^T xr that accumulate acc (the four rows a
@@ -50,9 +51,13 @@ template <> struct Mma<double> {
     static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
 };
 
-// Row tiles whose D entries a wave requests together.
+// Row tiles whose D entries a wave requests together: 6 with 32-bit
+// arithmetic, 4 in FP64 (twice the registers per value); the wide variant
+// takes 9, so that with up to 288 sampled rows (18 tiles, 9 per wave) every
+// wave makes a single round trip to memory.
 template <typename F> struct GroupTiles { static constexpr int value = 6; };
 template <> struct GroupTiles<double> { static constexpr int value = 4; };
+constexpr int kWideTiles = 9;
 
 }  // namespace
 
@@ -71,13 +76,12 @@ bool pass16_ok(int dtype, int R, int smax) {
 
 namespace {
 
-template <typename T, typename F, int R, bool LIT>
+template <typename T, typename F, int R, bool LIT, int GT>
 __device__ __forceinline__ void pass16_side(const SideArgs& S, int tile, double zeta, float zeta_f, char* lds) {
     typedef Mma<F> M;
     typedef typename M::v4 v4;
     constexpr int KR = (R + 3) / 4;                  // k-steps over the factor index
     constexpr int NB = (2 * KR + 4) * 64;            // operand block of one row tile
-    constexpr int GT = GroupTiles<F>::value;
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ct = w & 1, rh = w >> 1;               // column tile of the wave, half of the row tiles
@@ -240,10 +244,9 @@ __device__ __forceinline__ void pass16_side(const SideArgs& S, int tile, double 
     }
 }
 
-template <typename T, typename F, int R, bool LIT>
-__global__ __launch_bounds__(256) void pass16_kernel(PassArgs a) {
+template <typename T, typename F, int R, bool LIT, int GT>
+__device__ __forceinline__ void pass16_body(const PassArgs& a, char* lds) {
     if (a.st->stop) return;
-    extern __shared__ char lds[];
     // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so item
     // b = xcd * per + slot gives each XCD a contiguous range of column tiles
     const int nt0 = a.side[0].nwg;
@@ -251,28 +254,47 @@ __global__ __launch_bounds__(256) void pass16_kernel(PassArgs a) {
     const int per = (int)(gridDim.x >> 3);
     const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (b >= nt) return;
-    if (b < nt0) pass16_side<T, F, R, LIT>(a.side[0], b, a.zeta, a.zeta_f, lds);
-    else pass16_side<T, F, R, LIT>(a.side[1], b - nt0, a.zeta, a.zeta_f, lds);
+    if (b < nt0) pass16_side<T, F, R, LIT, GT>(a.side[0], b, a.zeta, a.zeta_f, lds);
+    else pass16_side<T, F, R, LIT, GT>(a.side[1], b - nt0, a.zeta, a.zeta_f, lds);
+}
+
+template <typename T, typename F, int R, bool LIT>
+__global__ __launch_bounds__(256) void pass16_kernel(PassArgs a) {
+    extern __shared__ char lds[];
+    pass16_body<T, F, R, LIT, GroupTiles<F>::value>(a, lds);
+}
+
+// The wide variant (32-bit arithmetic, padded rank at most 12, at most 288
+// sampled rows per side): every wave's loads in one group, with the register
+// budget of three waves per SIMD (as many as the launch needs at n = 10^4;
+// padded rank 16 would need more).
+template <typename T, typename F, int R, bool LIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void pass16_wide_kernel(PassArgs a) {
+    extern __shared__ char lds[];
+    pass16_body<T, F, R, LIT, kWideTiles>(a, lds);
 }
 
 template <typename T, typename F, int R>
 hipError_t pass16_r(const PassArgs& a, hipStream_t s) {
     const unsigned nb = (unsigned)(a.side[0].nwg + a.side[1].nwg);
     const unsigned grid = (nb + 7) / 8 * 8;          // a whole number of rounds over the 8 XCDs
-    const size_t lds = pass16_lds_bytes(0, R, std::max(a.side[0].s, a.side[1].s));
+    const int smax = std::max(a.side[0].s, a.side[1].s);
+    const size_t lds = pass16_lds_bytes(0, R, smax);
+    if constexpr (sizeof(F) == 4 && R <= 12) {
+        if ((smax + 15) / 16 <= 2 * kWideTiles) {
+            if (a.err_mode == 0) pass16_wide_kernel<T, F, R, true><<<grid, 256, lds, s>>>(a);
+            else pass16_wide_kernel<T, F, R, false><<<grid, 256, lds, s>>>(a);
+            return hipGetLastError();
+        }
+    }
     if (a.err_mode == 0) pass16_kernel<T, F, R, true><<<grid, 256, lds, s>>>(a);
     else pass16_kernel<T, F, R, false><<<grid, 256, lds, s>>>(a);
     return hipGetLastError();
 }
 
+// (padded ranks 8..16 only: smaller ranks take the vector pass)
 #define IRCUR_RANK_SWITCH16(FN, T, F, R, ...)                   \
     switch (R) {                                                \
-        case 1: return FN<T, F, 1>(__VA_ARGS__);                \
-        case 2: return FN<T, F, 2>(__VA_ARGS__);                \
-        case 3: return FN<T, F, 3>(__VA_ARGS__);                \
-        case 4: return FN<T, F, 4>(__VA_ARGS__);                \
-        case 5: return FN<T, F, 5>(__VA_ARGS__);                \
-        case 6: return FN<T, F, 6>(__VA_ARGS__);                \
         case 8: return FN<T, F, 8>(__VA_ARGS__);                \
         case 10: return FN<T, F, 10>(__VA_ARGS__);              \
         case 12: return FN<T, F, 12>(__VA_ARGS__);              \
