@@ -183,7 +183,6 @@ struct ircur_ctx {
     void* rowJt = nullptr;
     size_t csvd_lds = 0;
     double* Xr = nullptr;           // its exchange block (sJ16 x 16)
-    double* WQ = nullptr;           // its warm start, formed by the core launch (sJ16 x 16)
     std::vector<double> zsched;     // the caller's threshold schedule (empty: geometric)
     int32_t* Icur = nullptr;        // index sets of an export (device)
     int32_t* Jcur = nullptr;
@@ -297,7 +296,7 @@ void free_all(ircur_ctx* c) {
     void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
                     c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Xr, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
-                    c->info, c->hist, c->rowIt, c->rowJt, c->WQ};
+                    c->info, c->hist, c->rowIt, c->rowJt};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (c->Ipin) (void)hipHostFree(c->Ipin);
@@ -422,13 +421,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
         ca.n1 = p.n1; ca.n2 = p.n2; ca.At = c->At[cur]; ca.B = c->B[cur];
         ca.zeta = zeta; ca.zeta_f = zf; ca.M = c->M; ca.MA = c->MA; ca.MB = nullptr; ca.st = c->st;
         ca.Abc = c->Abc; ca.Bsc = c->Bsc;
-        ca.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
-        ca.r = p.r;
-        ca.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
-        ca.prevV = c->prevV; ca.WQ = c->WQ;
-        ca.tol = p.svd_tol > 0 ? p.svd_tol : (p.dtype == IRCUR_F64 ? 1e-13 : (p.dtype == IRCUR_F32 ? 1e-9 : 1e-7));
-        ca.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
-        HIPCHK(c, launch_core_warm(ca, p.dtype, c->R, s));
+        HIPCHK(c, launch_core(ca, p.dtype, c->R, s));
         CsvdArgs ka{};
         ka.D = c->D; ka.ldD = p.ldD; ka.I = Id; ka.J = Jd; ka.sI = p.sI; ka.sJ = p.sJ;
         ka.r = p.r; ka.R = c->R; ka.n1 = p.n1; ka.n2 = p.n2;
@@ -441,7 +434,7 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
         ka.tol_e = (p.dtype == IRCUR_BF16 && !(p.svd_tol > 0)) ? 1e-2 : 0.0;
         ka.warm = k == 0 ? 0 : (sameJ ? 1 : 2);
         ka.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
-        ka.prevV = c->prevV; ka.WQ = c->WQ; ka.Zp = c->Zp; ka.Gp = c->Gp; ka.Xr = c->Xr; ka.rp = c->rp;
+        ka.prevV = c->prevV; ka.Zp = c->Zp; ka.Gp = c->Gp; ka.Xr = c->Xr; ka.rp = c->rp;
         ka.W = c->W; ka.V = c->V; ka.sigma = c->sigma;
         ka.rowI = c->rowI; ka.rowJ = c->rowJ; ka.qs = row_stride(c->R, (int)c->fsz);
         ka.rowIt = c->rowIt; ka.rowJt = c->rowJt;
@@ -746,7 +739,6 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         TRY(dalloc(c, &c->Gp, (size_t)c->Gc * 768));
         TRY(dalloc(c, &c->prevV, sJ16 * 16));
         TRY(dalloc(c, &c->Xr, sJ16 * 16));
-        TRY(dalloc(c, &c->WQ, sJ16 * 16));
         if (!c->rp) TRY(dalloc(c, &c->rp, (size_t)c->Gc));
         else { (void)hipFree(c->rp); c->rp = nullptr; TRY(dalloc(c, &c->rp, (size_t)c->Gc)); }
         HIPCHK(c, hipMemset(c->Xr, 0, sJ16 * 16 * sizeof(double)));

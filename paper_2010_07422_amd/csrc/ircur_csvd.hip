@@ -2,8 +2,9 @@
 // (FP64 subspace arithmetic, ranks r <= 16):
 //
 //   core    M = [D - S_{k+1}]_{I,J}, S_{k+1} = T_zeta[D - L_k] on the block
-//           (eq. (4), (5)), gathered straight into LDS: workgroup g owns the
-//           16 rows I_{16g .. 16g+15} of M;
+//           (eq. (4), (5)), gathered by the core launch on every compute
+//           unit and loaded into LDS here: workgroup g owns the 16 rows
+//           I_{16g .. 16g+15} of M;
 //   svd     an orthonormal basis Q (|J| x 16) whose first r columns span the
 //           top-r right singular subspace of M (section 3.1), by subspace
 //           iteration on A = M^T M accelerated with Chebyshev filters;
@@ -113,6 +114,15 @@ __device__ __forceinline__ void sum_parts2(const double* b1, size_t s1, const do
     }
     r1 = x;
     r2 = y;
+}
+
+// Entry (b, c) of the starting block: rows past |J| and columns past `live`
+// zero; wanted columns from the loaded value v (warm 1: every column), the
+// others pseudo-random in [-1, 1].
+__device__ __forceinline__ double x0_entry(int warm, double v, int b, int c, int sJ, int r, int live, uint64_t salt) {
+    if (b >= sJ || c >= live) return 0.0;
+    if (warm == 1 || (warm == 2 && c < r)) return v;
+    return rnd_unit(salt, (uint64_t)(b * 16 + c));
 }
 
 }  // namespace
@@ -252,8 +262,10 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     (void)spare;
 
     // ---- load: the core launch's M block (row-tiled layout), A_k[I_blk, :] and the
-    // orthonormal warm start it formed (one round trip; the core launch gathered
-    // and thresholded the block on every compute unit) ----
+    // starting block X0 (one round trip; the core launch gathered and
+    // thresholded the block on every compute unit).  X0: the previous basis
+    // (warm == 1), else B_k[:, J]^T (warm == 2) or nothing (warm == 0) in the
+    // wanted columns and pseudo-random entries in the others ----
     {
         const double* __restrict__ src = a.MA + (size_t)wg * KS * 64;   // row tile wg: KS blocks of 64
         constexpr int UL = 32;            // doubles per thread (|J| <= 512)
@@ -261,9 +273,14 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #pragma unroll
         for (int u = 0; u < UL; ++u) mv[u] = src[min(tid + NT * u, KS * 64 - 1)];   // (clamped: no branch per load)
         const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
+        // (the source of X0 is uniform: one load per entry, clamped in bounds)
+        const double* __restrict__ xs0 = a.warm == 1 ? a.prevV : a.Bsc;
         double wv[18];
 #pragma unroll
-        for (int u = 0; u < 18; ++u) wv[u] = a.WQ[min(tid + NT * u, 16 * sJ16 - 1)];
+        for (int u = 0; u < 18; ++u) {
+            const int e = min(tid + NT * u, 16 * sJ16 - 1), b = e >> 4, c = e & 15;
+            wv[u] = xs0[a.warm == 1 ? e : (c < r ? c : 0) * sJ16 + b];
+        }
         // the run state is read with the loads above in flight; a stopped run
         // returns before it writes anything
         if (a.st->stop) return;
@@ -278,10 +295,14 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         Ab[tid] = (tid >> 4) < nb ? av : 0.0;
 #pragma unroll
         for (int u = 0; u < 18; ++u) {
-            const int e = tid + NT * u;
-            if (e < 16 * sJ16) X[(e >> 4) * XS + (e & 15)] = wv[u];
+            const int e = tid + NT * u, b = e >> 4, c = e & 15;
+            if (e < 16 * sJ16) X[b * XS + c] = x0_entry(a.warm, wv[u], b, c, sJ, r, live, a.salt);
         }
-        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) X[(e >> 4) * XS + (e & 15)] = a.WQ[e];   // |J| > 288
+        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) {                 // |J| > 288
+            const int b = e >> 4, c = e & 15;
+            X[b * XS + c] = x0_entry(a.warm, a.warm == 1 ? a.prevV[e] : a.Bsc[(size_t)(c < r ? c : 0) * sJ16 + b],
+                                     b, c, sJ, r, live, a.salt);
+        }
         // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
         for (int e = tid; e < ntl * 256; e += NT) {
             const int b = 16 * t0 + (e >> 4), c = e & 15;
@@ -294,6 +315,16 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
     const int min_passes = 1;
     CPHASE(0);
+    // the previous basis is tested as it stands (after one Cholesky QR pass:
+    // its columns are orthonormal to within the previous launch's tolerance);
+    // the other starting blocks are not orthonormal and never pass a test, so
+    // their first product with M^T M is a plain power step and the Cholesky
+    // QR that follows it orthonormalises M^T M X0 (the span that the power
+    // step from an orthonormalised X0 would reach)
+    if (a.warm == 1) {
+        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, LiT, dead, cst, scr, a.salt + 17);
+        QADD(q);
+    }
     CPHASE(1);
 
     // ---- subspace iteration -------------------------------------------------
@@ -301,7 +332,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     double* Gp = a.Gp + (size_t)wg * 768;
     uint32_t nbar = 0;
     int it = 0;                 // applications of A = M^T M
-    bool test = true;           // this application tests Q (X orthonormal)
+    bool test = a.warm == 1;    // this application tests Q (X orthonormal)
     bool power = true;          // the current sweep uses scaled power steps
     bool last_power = true;     // ... and the sweep before it
     double rate = 1.0;          // per-degree residual factor expected of the sweep
@@ -792,110 +823,6 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         (void)c_start; (void)r_start;
     }
 #endif
-}
-
-// ---- warm start (one more workgroup of the core launch) ----------------------
-// X0 (|J| x 16): IRCUR-R keeps B_k[:, J]^T as the wanted columns, the extra
-// ones (and every column of a cold start) pseudo-random; with the index set of
-// the previous iteration the previous basis.  Orthonormalised by Cholesky QR
-// (as in the SVD's sweeps) into WQ while the other workgroups gather the core.
-size_t warm_lds_bytes(int sJ) {
-    const size_t sJ16 = ((size_t)sJ + 15) / 16 * 16;
-    return (17 * sJ16 + 2 * 16 * XS + 16 + 4 * 256 + 32) * sizeof(double) + 64 * sizeof(int);
-}
-
-template <typename F>
-__device__ void warm_body(const CoreArgs& a) {
-    extern __shared__ double smem[];
-    const int tid = threadIdx.x;
-#ifdef IRCUR_PHASE_PROFILE
-    const uint64_t w0_ = __builtin_amdgcn_s_memrealtime();
-#endif
-    const int sJ = a.sJ, sJ16 = ((sJ + 15) / 16) * 16, r = a.r, live = min(16, sJ);
-    double* X = smem;
-    double* Gs = X + sJ16 * XS;
-    double* LiT = Gs + 16 * XS;
-    double* cst = LiT + 16 * XS;
-    double* scr = cst + 16;               // 4 x 256 + 32
-    int* dead = (int*)(scr + 4 * 256 + 32);
-    const F* __restrict__ B = (const F*)a.B;
-    // the run state first (its loads overlap the ones below)
-    const int32_t kd = a.st->k_done;
-    const double el = a.st->e_last;
-    const int tot = 16 * sJ16;
-    for (int e0 = tid; e0 < tot; e0 += NT * 18) {
-        // indices, then factor entries / previous basis, 18 per thread in flight
-        int jb[18];
-#pragma unroll
-        for (int u = 0; u < 18; ++u) jb[u] = a.J[min((e0 + NT * u) >> 4, sJ - 1)];
-        double v[18];
-#pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            const int e = min(e0 + NT * u, tot - 1), c = e & 15;
-            if (a.warm == 2) v[u] = (double)B[(int64_t)(c < r ? c : 0) * a.n2 + jb[u]];
-            else v[u] = a.warm == 1 ? a.prevV[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            const int e = e0 + NT * u;
-            if (e >= tot) continue;
-            const int b = e >> 4, c = e & 15;
-            double x = 0.0;
-            if (b < sJ && c < live) {
-                if (a.warm == 2) x = c < r ? v[u] : rnd_unit(a.salt, (uint64_t)e);
-                else x = a.warm == 1 ? v[u] : rnd_unit(a.salt, (uint64_t)e);
-            }
-            X[b * XS + c] = x;
-        }
-    }
-    __syncthreads();
-    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (kd > 0 ? el : 1.0)) : a.tol;
-    const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
-#ifdef IRCUR_PHASE_PROFILE
-    const uint64_t w1_ = __builtin_amdgcn_s_memrealtime();
-#endif
-    (void)cholqr(X, sJ16, sJ, live, kappa2_one, 1, Gs, LiT, dead, cst, scr, a.salt + 17);
-    for (int e = tid; e < tot; e += NT) a.WQ[e] = X[(e >> 4) * XS + (e & 15)];
-#ifdef IRCUR_PHASE_PROFILE
-    if (tid == 0) {
-        const uint64_t w2_ = __builtin_amdgcn_s_memrealtime();
-        a.st->phase[11] += w1_ - w0_;
-        a.st->phase[12] += w2_ - w1_;
-    }
-#endif
-}
-
-template <typename T, typename F, int R>
-__global__ __launch_bounds__(256) void core_warm_kernel(CoreArgs a) {
-    if (a.st->stop) return;
-    // the warm start takes the first workgroup (dispatched first: it is the
-    // longest), the core gather the others
-    if (blockIdx.x > 0) core_body<T, F, R>(a, (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x);
-    else warm_body<F>(a);
-}
-
-template <typename T, typename F, int R>
-static hipError_t core_warm_r(const CoreArgs& a, hipStream_t s) {
-    const int64_t total = (int64_t)a.sI * a.sJ;
-    const unsigned grid = (unsigned)((total + 255) / 256) + 1;
-    const size_t lds = warm_lds_bytes(a.sJ);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)core_warm_kernel<T, F, R>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    core_warm_kernel<T, F, R><<<grid, 256, lds, s>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_core_warm(const CoreArgs& a, int dtype, int R, hipStream_t s) {
-    if (R > 16) return hipErrorInvalidValue;
-    if (dtype == 0) { IRCUR_RANK_SWITCH(core_warm_r, double, double, R, a, s) }
-    if (dtype == 1) { IRCUR_RANK_SWITCH(core_warm_r, float, float, R, a, s) }
-    if (dtype == 2) { IRCUR_RANK_SWITCH(core_warm_r, bf16_t, float, R, a, s) }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s) {

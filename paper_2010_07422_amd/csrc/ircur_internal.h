@@ -130,15 +130,6 @@ struct CoreArgs {
     double* Abc;
     double* Bsc;
     DevState* st;
-    // Warm start of the one-launch SVD, formed by one more workgroup of the
-    // core launch (see launch_core_warm): the block X0 (|J| x 16; r wanted
-    // columns) orthonormalised by Cholesky QR into WQ (sJ16 x 16, doubles).
-    int32_t warm;          // 0 random, 1 previous basis prevV, 2 B_k[:, J]^T and random extras
-    int32_t r;
-    uint64_t salt;
-    const double* prevV;   // sJ16 x 16
-    double* WQ;
-    double tol, tol_e;     // the SVD's tolerance (a second Cholesky QR pass follows from it)
 };
 
 struct SvdArgs {
@@ -201,10 +192,10 @@ struct CsvdArgs {
     int32_t max_it;        // cap on applications of M^T M
     double tol;
     double tol_e;          // > 0: the tolerance is max(tol, tol_e * e_k) (e_0 = 1)
-    int32_t warm;          // 0 random, 1 previous basis, 2 B_k[:, J]^T
-    uint64_t salt;
-    double* prevV;         // sJ16 x 16: basis of the previous launch (out; the next warm start)
-    const double* WQ;      // sJ16 x 16: the orthonormal warm start formed by the core launch
+    int32_t warm;          // starting block: 0 random, 1 previous basis prevV, 2 B_k[:, J]^T
+                           // (from Bsc) with pseudo-random extra columns
+    uint64_t salt;         // pseudo-random entries of the starting block
+    double* prevV;         // sJ16 x 16: basis of the previous launch (in for warm == 1; out)
     double* Zp;            // G x sJ16 x 16 partials
     double* Gp;            // G x 3 x 256 partials (Y^T Y, Y^T A_blk, B_k[:, J] Q)
     double* Xr;            // sJ16 x 16: the next block (exchange)
@@ -345,8 +336,6 @@ size_t pass_split_bytes(int dtype, int R);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 // Core gather and top-r SVD in one launch; its LDS bytes.
 hipError_t launch_csvd(const CsvdArgs& a, int dtype, size_t lds_bytes, hipStream_t s);
-// The core launch with one more workgroup that forms the SVD's warm start.
-hipError_t launch_core_warm(const CoreArgs& a, int dtype, int R, hipStream_t s);
 size_t csvd_lds_bytes(int sJ, int G);
 hipError_t launch_set_bar(DevState* st, hipStream_t s);
 size_t svd_lds_bytes(int sJ, int bs16, int P);
