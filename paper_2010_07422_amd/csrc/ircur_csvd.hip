@@ -772,48 +772,11 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             a.info->iters = it;
             a.info->kept = kept;
             a.info->resid = res;
+            a.info->bx = live > r ? bx : -1.0;          // (the gap: the finalize launch)
+            a.info->gap = -1.0;
             if (!conv) a.st->svd_capped = 1;
             if (kept < r && Gy[0] > 0.0) a.st->rank_drop = 1;
         }
-    }
-    // gap estimate sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr)),
-    // lambda_min(Gy_rr) = 1 / ||Ly^-1||_2^2 by power steps on Ly^-T Ly^-1; on
-    // the last workgroup, while the first writes the small outputs
-    if (wg == G - 1) {
-        double gap = -1.0;
-        if (live > r && w4 == 0) {
-            double v = l64 < r ? 1.0 : 0.0, lam = 0.0;
-            for (int s = 0; s < 8; ++s) {
-                red[l64] = v;
-                __builtin_amdgcn_wave_barrier();
-                double w = 0.0;
-                if (l64 < 16) {
-                    double m_[16], v_[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[k * XS + l64]; v_[k] = red[k]; }
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) w = __builtin_fma(m_[k], v_[k], w);
-                }
-                __builtin_amdgcn_wave_barrier();
-                red[l64] = w;
-                __builtin_amdgcn_wave_barrier();
-                double u = 0.0;
-                if (l64 < 16) {
-                    double m_[16], v_[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) { m_[k] = LiT[l64 * XS + k]; v_[k] = red[k]; }
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) u = __builtin_fma(m_[k], v_[k], u);
-                }
-                __builtin_amdgcn_wave_barrier();
-                const double nv = __builtin_sqrt(wave_sum_dpp(u * u));
-                const double vv = __builtin_sqrt(wave_sum_dpp(v * v));
-                lam = vv > 0.0 ? nv / vv : 0.0;
-                v = nv > 0.0 ? u / nv : 0.0;
-            }
-            gap = __builtin_sqrt(fmax(bx, 0.0) * lam);
-        }
-        if (tid == 0) a.info->gap = gap;
     }
     CPHASE(10);
 #ifdef IRCUR_PHASE_PROFILE

@@ -69,6 +69,9 @@ struct SvdInfo {
     int32_t kept;
     double resid;        // max_i ||M^T w_i - sigma_i v_i|| / sigma_1
     double gap;          // sigma_{r+1} / sigma_r (Ritz estimate, 0 if p == r)
+    double bx;           // one-launch SVD: the extra columns' largest Rayleigh quotient
+                         // (~ sigma_{r+1}^2; -1 without extra columns), which the
+                         // finalize launch turns into gap
 };
 
 // Arguments of the fused row/column pass.  "Side" 0 is the row pass over
@@ -226,6 +229,11 @@ struct FinArgs {
     double eps;
     double* hist;          // e history
     DevState* st;
+    // one-launch SVD (else nullptr): a second workgroup estimates the gap
+    // sigma_{r+1} / sigma_r of iteration k from info->bx and Ly^-T (R x R)
+    const double* TAd;
+    SvdInfo* info;
+    int32_t R;
 };
 
 // Export of the last completed iteration (C, R, S blocks), factor dtype out.

@@ -113,3 +113,36 @@ def test_caller_threshold_schedule_matches_oracle():
     ref_g = O.ircur(p.D, r, s1, s2, p.Lmax, 0.7, 0.0, K, seed=3, resample=True)
     assert O.factored_rel_diff(A, B, ref_g.A, ref_g.B) > 1e-8 or not np.allclose(h, ref_g.e_hist)
     ctx.close()
+
+
+def test_gap_estimate_bounds_exact_spectrum():
+    """The per-iteration estimate of sigma_{r+1} / sigma_r (section 3.1: H_r
+    is unique only while sigma_r > sigma_{r+1}) against the exact ratio of
+    the oracle's core at the same iteration (n = 1000, r = 5, FP64, IRCUR-R,
+    8 iterations).  The estimate takes the extra columns' largest Rayleigh
+    quotient, which cannot exceed sigma_{r+1}^2 once the wanted columns span
+    the top-r subspace: it is a lower bound, and close to the ratio while
+    the ratio is large (the extra columns follow the next directions)."""
+    torch = require_gpu()
+    n, r, K = 1000, 5, 8
+    p = synth.planted(n, n, r, 0.1, seed=11)
+    s = synth.sample_size(4, r, n)
+    print(f"case gap estimate n={n} r={r} s={s} f64, {K} iterations", flush=True)
+    ctx, Dd = _ctx(torch, p.D, torch.float64, r, s, s, p.Lmax, eps=0.0, max_iter=K, seed=2, resample=True)
+    it, e, rc = ctx.solve()
+    assert it == K
+    _, gaps, kept = ctx.svd_history()
+    A = np.zeros((n, r)); B = np.zeros((r, n))
+    exact = []
+    for k in range(K):
+        I, J = sampler.draw_IJ(2, sampler.stream_id(k, True), n, n, s, s)
+        out = O.step(p.D, A, B, I, J, p.Lmax * 0.7 ** k, r)
+        sv = np.linalg.svd(out["M"], compute_uv=False)
+        exact.append(sv[r] / sv[r - 1])
+        A, B = out["A1"], out["B1"]
+    exact = np.array(exact); gaps = np.array(gaps)
+    print("gap estimate", np.round(gaps, 4), "exact", np.round(exact, 4), flush=True)
+    assert np.all(np.isfinite(gaps)) and np.all(gaps >= 0.0)
+    assert np.all(gaps <= exact * (1.0 + 1e-6) + 1e-12)
+    assert gaps[0] >= 0.5 * exact[0]
+    ctx.close()
