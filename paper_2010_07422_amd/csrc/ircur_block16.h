@@ -74,10 +74,10 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // Outputs in LDS (each may be null): L (row stride XS, zero above the
 // diagonal and in rows >= live), T = L^-T (row stride XS), dead[0..15],
 // st[0] = number of dead columns below live, st[1] and st[2] = largest and
-// smallest d_j / G_jj of the columns kept.  scr: 32 doubles.  Called by every
-// thread; ends with a workgroup barrier.
+// smallest d_j / G_jj of the kept columns among the first nst.  scr: 32
+// doubles.  Called by every thread; ends with a workgroup barrier.
 __device__ __forceinline__ void chol16(const double* G_, int gs, int live, double tol, bool colrel, double* L_,
-                                       double* T_, int* dead, double* st_, double* scr_) {
+                                       double* T_, int* dead, double* st_, double* scr_, int nst = 16) {
     if (wave_id() == 0) {
         const ldouble* G = lp(G_);
         ldouble* scr = lp(scr_);
@@ -142,7 +142,7 @@ __device__ __forceinline__ void chol16(const double* G_, int gs, int live, doubl
         if (dead && l >= 32 && l < 48) dead[i] = (dm >> i) & 1;
         if (st_) {
             // pivot statistics over the kept columns (lanes 0-15: their own)
-            const bool kept = l < 16 && !((dm >> i) & 1);
+            const bool kept = l < 16 && l < nst && !((dm >> i) & 1);
             const double e = kept ? mypiv * __builtin_amdgcn_rcp(G[i * gs + i]) : 0.0;
             double emax = e, emin = kept ? e : __builtin_inf();
 #pragma unroll

@@ -495,14 +495,14 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
     c->have_prevV = true;
     c->lastJ.assign(Jhost, Jhost + p.sJ);
 
-    const PassArgs pa = pass_args(c, k, Id, Jd);
+    PassArgs pa = pass_args(c, k, Id, Jd);
+    if (c->csvd) { pa.gapT = c->TAd; pa.gapinfo = c->info + k; pa.gapR = c->R; }   // the SVD's gap estimate
     HIPCHK(c, launch_pass(pa, p.dtype, c->R, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][3], s));
 
     FinArgs fa{};
     fa.part_row = c->part_row; fa.nrow = c->nwg_row; fa.part_col = c->part_col; fa.ncol = c->nwg_col;
     fa.k = k; fa.max_iter = p.max_iter; fa.eps = p.eps; fa.hist = c->hist; fa.st = c->st;
-    if (c->csvd) { fa.TAd = c->TAd; fa.info = c->info + k; fa.R = c->R; }
     HIPCHK(c, launch_finalize(fa, s));
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[slot][4], s));
     c->last_k = k;

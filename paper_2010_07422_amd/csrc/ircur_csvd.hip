@@ -116,6 +116,15 @@ __device__ __forceinline__ void sum_parts2(const double* b1, size_t s1, const do
     r2 = y;
 }
 
+// e / d for 0 <= e < 2^20 and d >= 1 from a float reciprocal (one correction
+// step either way makes it exact).
+__device__ __forceinline__ int div_small(int e, int d, float inv) {
+    int q = (int)((float)e * inv);
+    q -= q * d > e ? 1 : 0;
+    q += (q + 1) * d <= e ? 1 : 0;
+    return q;
+}
+
 // Entry (b, c) of the starting block: rows past |J| and columns past `live`
 // zero; wanted columns from the loaded value v (warm 1: every column), the
 // others pseudo-random in [-1, 1].
@@ -153,12 +162,16 @@ namespace {
 // X <- X L^-T with X^T X = L L^T.  A column is dead when its pivot falls to
 // 1e-14 of its own squared norm (a column that is merely small after a power
 // step is not mistaken for a dependent one).  A second pass runs when the
-// first pivots, relative to the column norms, spread by more than
-// `kappa2_one` (the rounding of X^T X would show in the orthogonality) and
-// whenever a column was found dependent (refilled with pseudo-random
-// entries); at most four passes.  Gs, LiT: 16 x XS; st: 4; scr: 4 x 256.
-__device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, int live, double kappa2_one, int min_passes,
-                                         double* Gs, double* LiT, int* dead, double* st, double* scr, uint64_t salt) {
+// first pivots of the wanted columns (the first nw), relative to the column
+// norms, spread by more than `kappa2_one` (the rounding of X^T X would show
+// in their orthogonality; the leading columns of the result depend only on
+// the leading columns of X, and the extra columns' orthogonality only sets
+// the filter interval) and whenever a column was found dependent (refilled
+// with pseudo-random entries); at most four passes.  Gs, LiT: 16 x XS; st:
+// 4; scr: 4 x 256.
+__device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, int live, int nw, double kappa2_one,
+                                         int min_passes, double* Gs, double* LiT, int* dead, double* st, double* scr,
+                                         uint64_t salt) {
     const int KS = sJ16 / 4, nt = sJ16 / 16;
     int need = min_passes;
     QTimes qt = {0, 0, 0};
@@ -171,7 +184,7 @@ __device__ __forceinline__ QTimes cholqr(double* X, int sJ16, int rows_valid, in
     for (int pass = 0; pass < 4; ++pass) {
         gram16(X, KS, scr, Gs);
         QPHASE(g);
-        chol16(Gs, XS, live, 1e-14, true, nullptr, LiT, dead, st, scr);
+        chol16(Gs, XS, live, 1e-14, true, nullptr, LiT, dead, st, scr, nw);
         QPHASE(c);
         xmul16(X, nt, LiT);
         QPHASE(x);
@@ -261,6 +274,8 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     int* spare = Il + 16;                 // 16
     (void)spare;
 
+    int32_t kd0;                          // run state: completed iterations, last e
+    double el0;
     // ---- load: the core launch's M block (row-tiled layout), A_k[I_blk, :] and the
     // starting block X0 (one round trip; the core launch gathered and
     // thresholded the block on every compute unit).  X0: the previous basis
@@ -273,16 +288,17 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #pragma unroll
         for (int u = 0; u < UL; ++u) mv[u] = src[min(tid + NT * u, KS * 64 - 1)];   // (clamped: no branch per load)
         const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
-        // (the source of X0 is uniform: one load per entry, clamped in bounds)
+        // (both sources hold 16 x sJ16 doubles, read in order: entry e is
+        // (b, c) = (e / 16, e % 16) of the previous basis, (e % sJ16, e / sJ16)
+        // of the compact copy of B_k[:, J])
         const double* __restrict__ xs0 = a.warm == 1 ? a.prevV : a.Bsc;
         double wv[18];
 #pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            const int e = min(tid + NT * u, 16 * sJ16 - 1), b = e >> 4, c = e & 15;
-            wv[u] = xs0[a.warm == 1 ? e : (c < r ? c : 0) * sJ16 + b];
-        }
+        for (int u = 0; u < 18; ++u) wv[u] = xs0[min(tid + NT * u, 16 * sJ16 - 1)];
         // the run state is read with the loads above in flight; a stopped run
         // returns before it writes anything
+        kd0 = a.st->k_done;
+        el0 = a.st->e_last;
         if (a.st->stop) return;
 #pragma unroll
         for (int u = 0; u < UL; ++u) {
@@ -293,15 +309,16 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             }
         }
         Ab[tid] = (tid >> 4) < nb ? av : 0.0;
+        const float inv16 = 1.0f / (float)sJ16;
 #pragma unroll
         for (int u = 0; u < 18; ++u) {
-            const int e = tid + NT * u, b = e >> 4, c = e & 15;
+            const int e = tid + NT * u;
+            const int c = a.warm == 1 ? (e & 15) : div_small(e, sJ16, inv16), b = a.warm == 1 ? (e >> 4) : e - c * sJ16;
             if (e < 16 * sJ16) X[b * XS + c] = x0_entry(a.warm, wv[u], b, c, sJ, r, live, a.salt);
         }
         for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) {                 // |J| > 288
-            const int b = e >> 4, c = e & 15;
-            X[b * XS + c] = x0_entry(a.warm, a.warm == 1 ? a.prevV[e] : a.Bsc[(size_t)(c < r ? c : 0) * sJ16 + b],
-                                     b, c, sJ, r, live, a.salt);
+            const int c = a.warm == 1 ? (e & 15) : div_small(e, sJ16, inv16), b = a.warm == 1 ? (e >> 4) : e - c * sJ16;
+            X[b * XS + c] = x0_entry(a.warm, xs0[e], b, c, sJ, r, live, a.salt);
         }
         // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
         for (int e = tid; e < ntl * 256; e += NT) {
@@ -311,7 +328,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     }
     __syncthreads();
     // a single Cholesky QR pass keeps X^T X within about 16 eps kappa^2 of I
-    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (a.st->k_done > 0 ? a.st->e_last : 1.0)) : a.tol;
+    const double tol_k = a.tol_e > 0.0 ? fmax(a.tol, a.tol_e * (kd0 > 0 ? el0 : 1.0)) : a.tol;
     const double kappa2_one = 0.01 * tol_k / (16.0 * 2.220446049250313e-16);
     const int min_passes = 1;
     CPHASE(0);
@@ -322,7 +339,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     // QR that follows it orthonormalises M^T M X0 (the span that the power
     // step from an orthonormalised X0 would reach)
     if (a.warm == 1) {
-        const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, LiT, dead, cst, scr, a.salt + 17);
+        const QTimes q = cholqr(X, sJ16, sJ, live, r, kappa2_one, min_passes, Gs, LiT, dead, cst, scr, a.salt + 17);
         QADD(q);
     }
     CPHASE(1);
@@ -596,7 +613,7 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         __syncthreads();
         CPHASE(8);
         if (j >= m) {
-            const QTimes q = cholqr(X, sJ16, sJ, live, kappa2_one, min_passes, Gs, LiT, dead, cst, scr,
+            const QTimes q = cholqr(X, sJ16, sJ, live, r, kappa2_one, min_passes, Gs, LiT, dead, cst, scr,
                                     a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
             QADD(q);
             test = true;

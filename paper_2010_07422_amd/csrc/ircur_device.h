@@ -45,6 +45,48 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Gap estimate of the one-launch SVD, made by a spare workgroup of the pass
+// launch that follows it: sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr))
+// with bx the extra columns' largest Rayleigh quotient (info->bx) and
+// lambda_min(Gy_rr) = 1 / lambda_max(Ly^-T Ly^-1) (T = Ly^-T, R x R), by eight
+// power steps on the first wave; sh: 64 doubles of LDS.
+__device__ __forceinline__ void gap_estimate(const double* T, SvdInfo* info, int R, double* sh) {
+    if (threadIdx.x >= 64) return;
+    const int l = threadIdx.x;
+    const double bx = info->bx;
+    double gap = -1.0;
+    if (bx >= 0.0) {
+        double tr[16], tc[16];                 // lane l < R: row l and column l of T = Ly^-T
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const bool in = l < R && k < R;
+            tr[k] = in ? T[l * R + k] : 0.0;
+            tc[k] = in ? T[k * R + l] : 0.0;
+        }
+        double v = l < R ? 1.0 : 0.0, lam = 0.0;
+        for (int s = 0; s < 8; ++s) {
+            sh[l] = v;
+            __builtin_amdgcn_wave_barrier();
+            double w = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w = __builtin_fma(tc[k], sh[k], w);    // (T^T v)_l
+            __builtin_amdgcn_wave_barrier();
+            sh[l] = w;
+            __builtin_amdgcn_wave_barrier();
+            double u = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) u = __builtin_fma(tr[k], sh[k], u);    // (T w)_l
+            __builtin_amdgcn_wave_barrier();
+            const double nv = __builtin_sqrt(wave_sum(u * u));
+            const double vv = __builtin_sqrt(wave_sum(v * v));
+            lam = vv > 0.0 ? nv / vv : 0.0;
+            v = nv > 0.0 ? u / nv : 0.0;
+        }
+        gap = __builtin_sqrt(bx * lam);
+    }
+    if (l == 0) info->gap = gap;
+}
+
 // Round a float to the nearest bfloat16 (ties to even); NaN stays NaN.
 __device__ __forceinline__ bf16_t to_bf16(float v) {
     uint32_t u = __float_as_uint(v);

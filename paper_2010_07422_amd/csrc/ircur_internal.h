@@ -70,8 +70,8 @@ struct SvdInfo {
     double resid;        // max_i ||M^T w_i - sigma_i v_i|| / sigma_1
     double gap;          // sigma_{r+1} / sigma_r (Ritz estimate, 0 if p == r)
     double bx;           // one-launch SVD: the extra columns' largest Rayleigh quotient
-                         // (~ sigma_{r+1}^2; -1 without extra columns), which the
-                         // finalize launch turns into gap
+                         // (~ sigma_{r+1}^2; -1 without extra columns), which a
+                         // spare workgroup of the pass launch turns into gap
 };
 
 // Arguments of the fused row/column pass.  "Side" 0 is the row pass over
@@ -108,6 +108,11 @@ struct PassArgs {
     float zeta_f;          // largest float <= zeta (exact float comparison)
     int32_t err_mode;
     const DevState* st;
+    // one-launch SVD (else nullptr): one more workgroup estimates the gap of
+    // the iteration's SVD from gapinfo->bx and Ly^-T (gapR x gapR)
+    const double* gapT;
+    SvdInfo* gapinfo;
+    int32_t gapR;
 };
 
 struct CoreArgs {
@@ -229,11 +234,6 @@ struct FinArgs {
     double eps;
     double* hist;          // e history
     DevState* st;
-    // one-launch SVD (else nullptr): a second workgroup estimates the gap
-    // sigma_{r+1} / sigma_r of iteration k from info->bx and Ly^-T (R x R)
-    const double* TAd;
-    SvdInfo* info;
-    int32_t R;
 };
 
 // Export of the last completed iteration (C, R, S blocks), factor dtype out.

@@ -83,6 +83,7 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
     if (a.st->stop) return;
     __shared__ F red[PassTree<T, F, R>::nred];
     __shared__ double redzd[PassTree<T, F, R>::nzd];
+    __shared__ double gsh[64];
     // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so work item
     // w = xcd * per + slot gives each XCD a contiguous range of (side, column
     // tile, row block) items: neighbouring tiles, which share the cache lines at
@@ -93,7 +94,10 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
     const int nbt = nb0 + a.side[1].nwg * ns1;
     const int per = (int)(gridDim.x >> 3);
     const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (b >= nbt) return;
+    if (b >= nbt) {
+        if (b == nbt && a.gapT) gap_estimate(a.gapT, a.gapinfo, a.gapR, gsh);   // (a spare workgroup)
+        return;
+    }
     if (b < nb0) {
         side_body<T, F, R, LIT>(a.side[0], b / ns0, b % ns0, a.zeta, a.zeta_f, red, redzd);
     } else {
@@ -104,57 +108,9 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
 
 // ------------------------------------------------------------- finalize ---
 
-// Gap estimate of the one-launch SVD (second workgroup of the finalize
-// launch, beside the stopping test): sigma_{r+1} / sigma_r ~ sqrt(bx /
-// lambda_min(Gy_rr)) with bx the extra columns' largest Rayleigh quotient
-// and lambda_min(Gy_rr) = 1 / lambda_max(Ly^-T Ly^-1), by eight power steps
-// on one wave.
-__device__ void gap_body(const FinArgs& a, double* sh) {
-    if (threadIdx.x >= 64) return;
-    const int l = threadIdx.x, R = a.R;
-    const double bx = a.info->bx;
-    double gap = -1.0;
-    if (bx >= 0.0) {
-        double tr[16], tc[16];                 // lane l < R: row l and column l of T = Ly^-T
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const bool in = l < R && k < R;
-            tr[k] = in ? a.TAd[l * R + k] : 0.0;
-            tc[k] = in ? a.TAd[k * R + l] : 0.0;
-        }
-        double v = l < R ? 1.0 : 0.0, lam = 0.0;
-        for (int s = 0; s < 8; ++s) {
-            sh[l] = v;
-            __builtin_amdgcn_wave_barrier();
-            double w = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) w = __builtin_fma(tc[k], sh[k], w);    // (T^T v)_l
-            __builtin_amdgcn_wave_barrier();
-            sh[l] = w;
-            __builtin_amdgcn_wave_barrier();
-            double u = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) u = __builtin_fma(tr[k], sh[k], u);    // (T w)_l
-            __builtin_amdgcn_wave_barrier();
-            const double nv = __builtin_sqrt(wave_sum(u * u));
-            const double vv = __builtin_sqrt(wave_sum(v * v));
-            lam = vv > 0.0 ? nv / vv : 0.0;
-            v = nv > 0.0 ? u / nv : 0.0;
-        }
-        gap = __builtin_sqrt(bx * lam);
-    }
-    if (l == 0) a.info->gap = gap;
-}
-
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
-    __shared__ double sh[4][256];
-    if (blockIdx.x == 1) {
-        // (no look at the stop flag, which the first workgroup may be setting:
-        // for an iteration that did not run this fills a record never read)
-        gap_body(a, sh[0]);
-        return;
-    }
     if (a.st->stop) return;
+    __shared__ double sh[4][256];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int w = threadIdx.x; w < a.nrow; w += 256) {
         v[0] += a.part_row[2 * w];
@@ -206,7 +162,7 @@ static hipError_t core_r(const CoreArgs& a, hipStream_t s) {
 template <typename T, typename F, int R>
 static hipError_t pass_r(const PassArgs& a, hipStream_t s) {
     const unsigned nb = (unsigned)(a.side[0].nwg * std::max(1, a.side[0].nsplit) +
-                                   a.side[1].nwg * std::max(1, a.side[1].nsplit));
+                                   a.side[1].nwg * std::max(1, a.side[1].nsplit)) + (a.gapT ? 1 : 0);
     const unsigned grid = (nb + 7) / 8 * 8;          // a whole number of rounds over the 8 XCDs
     if (a.err_mode == 0) pass_kernel<T, F, R, true><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
     else pass_kernel<T, F, R, false><<<grid, 64 * PassWaves<T, R>::value, 0, s>>>(a);
@@ -258,7 +214,7 @@ size_t pass_split_bytes(int dtype, int R) {
 }
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-    finalize_kernel<<<a.TAd ? 2 : 1, 256, 0, s>>>(a);
+    finalize_kernel<<<1, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

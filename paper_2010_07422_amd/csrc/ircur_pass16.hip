@@ -253,7 +253,10 @@ __device__ __forceinline__ void pass16_body(const PassArgs& a, char* lds) {
     const int nt = nt0 + a.side[1].nwg;
     const int per = (int)(gridDim.x >> 3);
     const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (b >= nt) return;
+    if (b >= nt) {
+        if (b == nt && a.gapT) gap_estimate(a.gapT, a.gapinfo, a.gapR, (double*)lds);   // (a spare workgroup)
+        return;
+    }
     if (b < nt0) pass16_side<T, F, R, LIT, GT>(a.side[0], b, a.zeta, a.zeta_f, lds);
     else pass16_side<T, F, R, LIT, GT>(a.side[1], b - nt0, a.zeta, a.zeta_f, lds);
 }
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
 
 template <typename T, typename F, int R>
 hipError_t pass16_r(const PassArgs& a, hipStream_t s) {
-    const unsigned nb = (unsigned)(a.side[0].nwg + a.side[1].nwg);
+    const unsigned nb = (unsigned)(a.side[0].nwg + a.side[1].nwg) + (a.gapT ? 1 : 0);
     const unsigned grid = (nb + 7) / 8 * 8;          // a whole number of rounds over the 8 XCDs
     const int smax = std::max(a.side[0].s, a.side[1].s);
     const size_t lds = pass16_lds_bytes(0, R, smax);
