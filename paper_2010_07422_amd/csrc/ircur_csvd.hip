@@ -116,22 +116,17 @@ __device__ __forceinline__ void sum_parts2(const double* b1, size_t s1, const do
     r2 = y;
 }
 
-// e / d for 0 <= e < 2^20 and d >= 1 from a float reciprocal (one correction
-// step either way makes it exact).
-__device__ __forceinline__ int div_small(int e, int d, float inv) {
-    int q = (int)((float)e * inv);
-    q -= q * d > e ? 1 : 0;
-    q += (q + 1) * d <= e ? 1 : 0;
-    return q;
-}
-
-// Entry (b, c) of the starting block: rows past |J| and columns past `live`
-// zero; wanted columns from the loaded value v (warm 1: every column), the
-// others pseudo-random in [-1, 1].
-__device__ __forceinline__ double x0_entry(int warm, double v, int b, int c, int sJ, int r, int live, uint64_t salt) {
-    if (b >= sJ || c >= live) return 0.0;
-    if (warm == 1 || (warm == 2 && c < r)) return v;
-    return rnd_unit(salt, (uint64_t)(b * 16 + c));
+// Pseudo-random entry i of the starting block in [-1, 1): the 32-bit
+// finaliser of MurmurHash3 applied to the salt plus i times the golden-ratio
+// constant.
+__device__ __forceinline__ double rnd_x0(uint64_t salt, int i) {
+    uint32_t h = (uint32_t)salt ^ (uint32_t)(salt >> 32) ^ ((uint32_t)i * 0x9E3779B9u);
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
 }  // namespace
@@ -288,13 +283,18 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #pragma unroll
         for (int u = 0; u < UL; ++u) mv[u] = src[min(tid + NT * u, KS * 64 - 1)];   // (clamped: no branch per load)
         const double av = a.Abc[(size_t)(a0 + (tid >> 4)) * 16 + (tid & 15)];
-        // (both sources hold 16 x sJ16 doubles, read in order: entry e is
-        // (b, c) = (e / 16, e % 16) of the previous basis, (e % sJ16, e / sJ16)
-        // of the compact copy of B_k[:, J])
-        const double* __restrict__ xs0 = a.warm == 1 ? a.prevV : a.Bsc;
-        double wv[18];
+        // previous basis (row-major, 16 per row): entries tid + NT u in order;
+        // B_k[:, J] (16 x sJ16): rows b = tid, tid + NT of each column, every
+        // load in bounds and coalesced (|J| <= 512)
+        const bool prev = a.warm == 1;
+        double wv[2][16];
 #pragma unroll
-        for (int u = 0; u < 18; ++u) wv[u] = xs0[min(tid + NT * u, 16 * sJ16 - 1)];
+        for (int u = 0; u < 32; ++u) {
+            const int h = u >> 4, c = u & 15;
+            const int i = prev ? min(tid + NT * u, 16 * sJ16 - 1)
+                               : (c < r ? c : 0) * sJ16 + min(tid + NT * h, sJ16 - 1);
+            wv[h][c] = (prev || a.warm == 2) ? (prev ? a.prevV : a.Bsc)[i] : 0.0;
+        }
         // the run state is read with the loads above in flight; a stopped run
         // returns before it writes anything
         kd0 = a.st->k_done;
@@ -309,16 +309,25 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             }
         }
         Ab[tid] = (tid >> 4) < nb ? av : 0.0;
-        const float inv16 = 1.0f / (float)sJ16;
+        // the starting block: rows past |J| and columns past `live` zero; the
+        // wanted columns (warm 2) or all of them (warm 1) from the loads; the
+        // other entries pseudo-random, filled below
+        if (prev) {
 #pragma unroll
-        for (int u = 0; u < 18; ++u) {
-            const int e = tid + NT * u;
-            const int c = a.warm == 1 ? (e & 15) : div_small(e, sJ16, inv16), b = a.warm == 1 ? (e >> 4) : e - c * sJ16;
-            if (e < 16 * sJ16) X[b * XS + c] = x0_entry(a.warm, wv[u], b, c, sJ, r, live, a.salt);
-        }
-        for (int e = tid + NT * 18; e < 16 * sJ16; e += NT) {                 // |J| > 288
-            const int c = a.warm == 1 ? (e & 15) : div_small(e, sJ16, inv16), b = a.warm == 1 ? (e >> 4) : e - c * sJ16;
-            X[b * XS + c] = x0_entry(a.warm, xs0[e], b, c, sJ, r, live, a.salt);
+            for (int u = 0; u < 32; ++u) {
+                const int e = tid + NT * u, b = e >> 4, c = e & 15;
+                if (e < 16 * sJ16) X[b * XS + c] = (b < sJ && c < live) ? wv[u >> 4][u & 15] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                const int h = u >> 4, c = u & 15, b = tid + NT * h;
+                if (b < sJ16) X[b * XS + c] = (b < sJ && c < live && c < r) ? wv[h][c] : 0.0;
+            }
+            const int c0 = a.warm == 2 ? r : 0;
+#pragma unroll 1
+            for (int c = c0; c < live; ++c)
+                for (int b = tid; b < sJ; b += NT) X[b * XS + c] = rnd_x0(a.salt, b * 16 + c);
         }
         // B_k[:, J_b] of this workgroup's slice rows (epilogue, Gamma')
         for (int e = tid; e < ntl * 256; e += NT) {
@@ -358,8 +367,9 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     double cs = 0.0, es = 0.0, sg1 = 0.0, sg = 0.0, scale = 1.0;
     double res = 0.0, res_sweep = -1.0;
     bool conv = false;
-    int plain_next = 0;         // tests whose sweep must use power steps
-    bool no_cheb = false;       // a Chebyshev sweep fell short of its prediction: power steps from here on
+    double widen = 1.0;         // filter interval [0, b]: b = 1.02 widen bx (the extra columns'
+                                // quotients estimate sigma_{r+1}^2 from below)
+    int cool = 0;               // tests whose sweep uses power steps (after a sweep that fell short)
     double bx_prev = -1.0;      // extra columns' largest quotient at the previous test
     double pred = 1.0;          // residual factor predicted for the current sweep
     double hi_t = 0.0, lo_t = 0.0;   // largest and smallest wanted quotients at the last test
@@ -497,13 +507,14 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
             // settled (2% between tests) and lies clearly below the wanted ones
             const bool stable = bx_prev > 0.0 && fabs(bx - bx_prev) <= 0.02 * bx;
             bx_prev = bx;
-            power = no_cheb || plain_next > 0 || !(bx > 0.0) || !(bx < 0.9 * lo) || !stable;
-            if (plain_next > 0) --plain_next;
+            power = cool > 0 || !(bx > 0.0) || !(bx < 0.9 * lo) || !stable;
+            if (cool > 0) --cool;
             if (power) {
                 cs = 0.0; es = 0.0;
                 scale = hi > 0.0 ? 1.0 / hi : 1.0;
             } else {
-                cs = 0.5 * bx; es = 0.5 * bx;
+                const double bb = fmin(1.02 * widen * bx, 0.95 * lo);
+                cs = 0.5 * bb; es = 0.5 * bb;
                 sg1 = es / (hi - cs);
                 sg = sg1;
                 scale = sg1 / es;
@@ -573,7 +584,13 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
 #endif
             if (conv || it >= a.max_it) break;        // X still holds the tested Q
             // a Chebyshev sweep that did not halve the residual: plain steps next
-            if (!last_power && res_sweep > 0.0 && res > res_sweep * __builtin_sqrt(pred)) no_cheb = true;
+            // a Chebyshev sweep that did not reach the square root of its
+            // predicted factor: the interval was too narrow (sigma_{r+1}^2
+            // above b); one power step, then a wider interval
+            if (!last_power && res_sweep > 0.0 && res > res_sweep * __builtin_sqrt(pred)) {
+                widen *= 1.05;
+                cool = 1;
+            }
             res_sweep = res;
             // degree of the sweep: enough for the residual to reach tol at `rate`
             m = 1;
