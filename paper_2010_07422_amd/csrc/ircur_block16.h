@@ -75,9 +75,12 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // diagonal and in rows >= live), T = L^-T (row stride XS), dead[0..15],
 // st[0] = number of dead columns below live, st[1] and st[2] = largest and
 // smallest d_j / G_jj of the kept columns among the first nst.  scr: 32
-// doubles.  Called by every thread; ends with a workgroup barrier.
+// doubles.  Called by every thread; ends with a workgroup barrier (sync), or
+// without one, the other waves returning at once (the caller then places the
+// barrier after their own work).
 __device__ __forceinline__ void chol16(const double* G_, int gs, int live, double tol, bool colrel, double* L_,
-                                       double* T_, int* dead, double* st_, double* scr_, int nst = 16) {
+                                       double* T_, int* dead, double* st_, double* scr_, int nst = 16,
+                                       bool sync = true) {
     if (wave_id() == 0) {
         const ldouble* G = lp(G_);
         ldouble* scr = lp(scr_);
@@ -158,7 +161,7 @@ __device__ __forceinline__ void chol16(const double* G_, int gs, int live, doubl
             }
         }
     }
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 // G = X^T X over the first 4 KS rows of X (row stride XS), 16 x 16 row-major

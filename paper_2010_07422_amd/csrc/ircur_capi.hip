@@ -436,7 +436,9 @@ int enqueue_iter(ircur_ctx* c, int k, const int32_t* Id, const int32_t* Jd, cons
         ka.salt = sm_mix(p.seed ^ (0xA24BAED4963EE407ull * (uint64_t)(k + 1)));
         ka.prevV = c->prevV; ka.Zp = c->Zp; ka.Gp = c->Gp; ka.Xr = c->Xr; ka.rp = c->rp;
         ka.W = c->W; ka.V = c->V; ka.sigma = c->sigma;
-        ka.rowI = c->rowI; ka.rowJ = c->rowJ; ka.qs = row_stride(c->R, (int)c->fsz);
+        // (the row form only for the vector pass; the matrix-core pass reads the tiles)
+        ka.rowI = c->p16 ? nullptr : c->rowI; ka.rowJ = c->p16 ? nullptr : c->rowJ;
+        ka.qs = row_stride(c->R, (int)c->fsz);
         ka.rowIt = c->rowIt; ka.rowJt = c->rowJt;
         ka.GmI = c->GmI; ka.GmJ = c->GmJ; ka.scaleJ = c->scaleJ; ka.TAd = c->TAd;
         ka.info = c->info + k; ka.st = c->st;

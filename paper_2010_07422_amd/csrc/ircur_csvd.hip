@@ -651,19 +651,6 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     }
 
     // ---- epilogue -------------------------------------------------------------
-    // H = Y^T A_blk and Gamma' = B_k[:, J] Q from the partials of the last test
-    {
-        const int ix = ((tid & 63) >> 4) * 16 + 64 * (tid >> 6) + (tid & 15);
-        double h, g2;
-        sum_parts2(a.Gp + 256 + tid, 768, a.Gp + 512 + tid, 768, G, h, g2);
-        H[ix] = h;
-        Gam2[ix] = g2;
-    }
-    // the next warm start keeps all columns (rows of this slice); the outputs use the first r
-    for (int e = tid; e < ntl * 256; e += NT) {
-        const int b = 16 * t0 + (e >> 4), c = e & 15;
-        a.prevV[b * 16 + c] = X[b * XS + c];
-    }
     double bx = 0.0;
     {
         double dg[16];
@@ -673,14 +660,29 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         for (int c = 0; c < 16; ++c)
             if (c >= r && c < live) bx = fmax(bx, dg[c]);
     }
-    __syncthreads();
-    for (int e = tid; e < ntl * 256; e += NT)              // (only the slice rows are read below)
-        if ((e & 15) >= r) X[(16 * t0 + (e >> 4)) * XS + (e & 15)] = 0.0;
-    if ((tid & 15) >= r) Gam2[tid] = 0.0;
-    // Gy_rr = Ly Ly^T; a pivot <= s eps max_j Gy_jj is a direction the Gram
-    // matrix cannot resolve (sigma below about sqrt(s eps) sigma_1): dropped
+    // wave 0: Gy_rr = Ly Ly^T; a pivot <= s eps max_j Gy_jj is a direction the
+    // Gram matrix cannot resolve (sigma below about sqrt(s eps) sigma_1):
+    // dropped.  Waves 1-3 meanwhile: H = Y^T A_blk and Gamma' = B_k[:, J] Q from
+    // the partials of the last test (columns >= r of Gamma' zero), the next
+    // starting basis (all columns of this slice's rows), and the columns >= r
+    // of the slice rows of X zeroed (the outputs use the first r)
     const double ptol = (double)(sI > sJ ? sI : sJ) * 2.220446049250313e-16;
-    chol16(Gy, 16, r, ptol, false, Ls, LiT, dead, nullptr, scr);
+    chol16(Gy, 16, r, ptol, false, Ls, LiT, dead, nullptr, scr, 16, false);
+    if (w4 != 0) {
+        for (int e = tid - 64; e < 256; e += NT - 64) {
+            const int ix = ((e & 63) >> 4) * 16 + 64 * (e >> 6) + (e & 15);
+            double h, g2;
+            sum_parts2(a.Gp + 256 + e, 768, a.Gp + 512 + e, 768, G, h, g2);
+            H[ix] = h;
+            Gam2[ix] = (ix & 15) >= r ? 0.0 : g2;
+        }
+        for (int e = tid - 64; e < ntl * 256; e += NT - 64) {
+            const int b = 16 * t0 + (e >> 4), c = e & 15;
+            a.prevV[b * 16 + c] = X[b * XS + c];
+            if (c >= r) X[b * XS + c] = 0.0;
+        }
+    }
+    __syncthreads();
     // Wt_blk = Y Ly^-T, Gamma = Ly^-1 H, TA = Ly^-T
     double* Wb = Gs;
     if (w4 == 0) {
@@ -720,10 +722,12 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
     __syncthreads();
     for (int e = tid; e < nb * R; e += NT) {
         const int ar = e / R, c = e - ar * R;
-        const int64_t base = (int64_t)(a0 + ar) * a.qs;
-        fput(a.rowI, base + c, Ab[ar * 16 + c], fd);
-        fput(a.rowI, base + R + c, Wb[ar * 16 + c], fd);
-        fput(a.rowI, base + 2 * R + c, Ab[ar * 16 + c] - Y[ar * 16 + c], fd);
+        if (a.rowI) {                                      // (the vector pass's row form)
+            const int64_t base = (int64_t)(a0 + ar) * a.qs;
+            fput(a.rowI, base + c, Ab[ar * 16 + c], fd);
+            fput(a.rowI, base + R + c, Wb[ar * 16 + c], fd);
+            fput(a.rowI, base + 2 * R + c, Ab[ar * 16 + c] - Y[ar * 16 + c], fd);
+        }
         a.W[(int64_t)(a0 + ar) * R + c] = Wb[ar * 16 + c];
     }
     // rows of this workgroup's slice: [B_k[:, J_b] | Q[b, :] | B_k[:, J_b] - Gamma' Q[b, :]^T],
@@ -748,11 +752,12 @@ __global__ __launch_bounds__(256) void csvd_kernel(CsvdArgs a) {
         const int bl = e / R, c = e - bl * R;
         const int b = 16 * t0 + bl;
         if (b >= sJ) continue;
-        const int64_t base = (int64_t)b * a.qs;
-        const double bcj = Bsl[bl * 16 + c];
-        fput(a.rowJ, base + c, bcj, fd);
-        fput(a.rowJ, base + R + c, X[b * XS + c], fd);
-        fput(a.rowJ, base + 2 * R + c, Zs[bl * 16 + c], fd);
+        if (a.rowJ) {
+            const int64_t base = (int64_t)b * a.qs;
+            fput(a.rowJ, base + c, Bsl[bl * 16 + c], fd);
+            fput(a.rowJ, base + R + c, X[b * XS + c], fd);
+            fput(a.rowJ, base + 2 * R + c, Zs[bl * 16 + c], fd);
+        }
         a.V[(int64_t)b * R + c] = X[b * XS + c];
     }
     // the same per-row data in the operand-tile order of the matrix-core pass:
