@@ -318,7 +318,8 @@ struct UBack {
     double* Mperp;                        // sI16 x sJ16: M - W_r Sigma V_r^T, zero padded
     double* Wr; double* Vr;               // sI x R, sJ x R singular vectors (columns >= r zero)
     double* Tp;                           // sJ x R: Q Ly^-T
-    double* X1; double* X2;               // sI x R, sJ x R: M_bar = X1 V_r^T + W_r X2^T
+    double* X1; double* X2;               // sI x R, sJ x R: M_bar = X1 V_r^T + W_r X2^T with
+    double* X1b; double* X2b;             // X1 = X1 + X1b, X2 = X2 + X2b (W side + V side)
     double* P1; double* P2;               // sI x R, sJ x R workspace
     double* dz;                           // this step's zeta gradient (one value)
     int32_t* flags;                       // bit 0: CG did not converge, bit 1: rank < r

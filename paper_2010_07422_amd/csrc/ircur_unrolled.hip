@@ -349,7 +349,8 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                     } else if (PH == 2) {
                         const int k = c - R, which = k / R, cr = k - which * R;
                         const double* srcd = rowside ? (which == 0 ? u.Wt : (which == 1 ? u.X1 : u.Wr)) : u.Tp;
-                        x = (F)srcd[(int64_t)a * R + cr];
+                        const int64_t ix = (int64_t)a * R + cr;
+                        x = (F)(rowside && which == 1 ? srcd[ix] + u.X1b[ix] : srcd[ix]);   // X1 = X1a + X1b
                     }
                 }
                 v[q] = x;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             vb[c] = inJ ? (F)u.Vr[(int64_t)bp * R + c] : F(0);
-            xb[c] = inJ ? (F)u.X2[(int64_t)bp * R + c] : F(0);
+            xb[c] = inJ ? (F)(u.X2[(int64_t)bp * R + c] + u.X2b[(int64_t)bp * R + c]) : F(0);   // X2a + X2b
         }
     }
     F acc[R];
@@ -674,9 +675,14 @@ __device__ int cg_solve(const gdouble* Mp, int sI16, int sJ16, int sI, int sJ, c
 #define UPHASE(i) do { } while (0)
 #endif
 
+// Two workgroups per instance: both form the shared set-up (identical
+// arithmetic, identical global writes), then workgroup 0 solves the W-side
+// systems and workgroup 1 the V-side ones, each writing its own part of
+// X1 = X1a + X1b and X2 = X2a + X2b (the consumer adds the two parts).
 __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ arr, int max_it, double tol) {
     extern __shared__ double smem[];
-    const UBack& u = arr[blockIdx.x];
+    const UBack& u = arr[blockIdx.x >> 1];
+    const int side = blockIdx.x & 1;
 #ifdef IRCUR_PHASE_PROFILE
     uint64_t t_prev = __builtin_amdgcn_s_memrealtime();
 #endif
@@ -722,7 +728,8 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
             sig[c] = c < r ? part[order[c]] : 0.0;
             sig2[c] = sig[c] * sig[c];
         }
-        if (!(sig[r - 1] > 2.220446049250313e-16 * (double)(sI > sJ ? sI : sJ) * sig[0])) gp(u.flags)[0] |= 2;
+        if (!(sig[r - 1] > 2.220446049250313e-16 * (double)(sI > sJ ? sI : sJ) * sig[0]))
+            __hip_atomic_fetch_or(u.flags, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     for (int e = tid; e < 256; e += NT) {
@@ -896,58 +903,60 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
     __syncthreads();
     UPHASE(12);
     int fail = 0;
-    // W side:  (sig_c^2 I - M_perp M_perp^T) x_c = rhs_c  (rhs in B4; B1 serves as scratch)
-    fail |= cg_solve<true>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B4, B2, B3, B1, part, cols, max_it, tol);
-    UPHASE(13);
-    // Qm = x / sigma (into B0), then M_perp^T Qm (sJ x 16) into B4
-    for (int e = tid; e < m16 * 16; e += NT) {
-        const int c = e & 15;
-        B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;
-    }
-    __syncthreads();
-    mm_rows_gA<true>(gp(u.Mperp), sJ16, B0, B4, sJ16, sI16, sJ);
-    __syncthreads();
-    // stash Qm in P1 and M_perp^T Qm in X2 (global)
-    for (int e = tid; e < sI * R; e += NT) {
-        const int a = e / R, c = e - a * R;
-        gp(u.P1)[e] = B0[a * 16 + c];
-    }
-    for (int e = tid; e < sJ * R; e += NT) {
-        const int b = e / R, c = e - b * R;
-        gp(u.X2)[e] = B4[b * 16 + c];
-    }
-    __syncthreads();
-    // V side:  (sig_c^2 I - M_perp^T M_perp) y_c = rhs_c
-    for (int e = tid; e < m16 * 16; e += NT) {
-        const int a = e >> 4, c = e & 15;
-        B1[e] = (a < sJ && c < R) ? gp(u.P2)[a * R + c] : 0.0;
-    }
-    __syncthreads();
-    UPHASE(14);
-    fail |= cg_solve<false>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
-    UPHASE(15);
-    for (int e = tid; e < m16 * 16; e += NT) {
-        const int c = e & 15;
-        B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;   // Um
-    }
-    __syncthreads();
-    mm_rows_gA<false>(gp(u.Mperp), sJ16, B0, B4, sI16, sJ16, sI);   // M_perp Um (sI x 16)
-    __syncthreads();
-    // X1 = Qm Sigma + M_perp Um - W_r Sigma^-1 Urr Sigma^-1,  X2 = M_perp^T Qm + Um Sigma
-    for (int e = tid; e < sI * R; e += NT) {
-        const int a = e / R, c = e - a * R;
-        double v = 0.0;
-        if (c < r) {
-            v = __builtin_fma(gp(u.P1)[e], sig[c], B4[a * 16 + c]);
-            for (int f = 0; f < r; ++f) v = __builtin_fma(-gp(u.Wr)[a * R + f], Urr[f * 16 + c] / (sig[f] * sig[c]), v);
+    if (side == 0) {
+        // W side:  (sig_c^2 I - M_perp M_perp^T) x_c = rhs_c  (rhs in B4; B1 serves as scratch)
+        fail |= cg_solve<true>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B4, B2, B3, B1, part, cols, max_it, tol);
+        UPHASE(13);
+        // Qm = x / sigma (into B0), then M_perp^T Qm (sJ x 16) into B4
+        for (int e = tid; e < m16 * 16; e += NT) {
+            const int c = e & 15;
+            B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;
         }
-        gp(u.X1)[e] = v;
+        __syncthreads();
+        mm_rows_gA<true>(gp(u.Mperp), sJ16, B0, B4, sJ16, sI16, sJ);
+        __syncthreads();
+        UPHASE(14);
+        // X1a = Qm Sigma - W_r Sigma^-1 Urr Sigma^-1,  X2a = M_perp^T Qm
+        for (int e = tid; e < sI * R; e += NT) {
+            const int a = e / R, c = e - a * R;
+            double v = 0.0;
+            if (c < r) {
+                v = B0[a * 16 + c] * sig[c];
+                for (int f = 0; f < r; ++f) v = __builtin_fma(-gp(u.Wr)[a * R + f], Urr[f * 16 + c] / (sig[f] * sig[c]), v);
+            }
+            gp(u.X1)[e] = v;
+        }
+        for (int e = tid; e < sJ * R; e += NT) {
+            const int b = e / R, c = e - b * R;
+            gp(u.X2)[e] = B4[b * 16 + c];
+        }
+    } else {
+        // V side:  (sig_c^2 I - M_perp^T M_perp) y_c = rhs_c  (rhs from P2)
+        for (int e = tid; e < m16 * 16; e += NT) {
+            const int a = e >> 4, c = e & 15;
+            B1[e] = (a < sJ && c < R) ? gp(u.P2)[a * R + c] : 0.0;
+        }
+        __syncthreads();
+        fail |= cg_solve<false>(gp(u.Mperp), sI16, sJ16, sI, sJ, sig2, r, B0, B1, B2, B3, B4, part, cols, max_it, tol);
+        for (int e = tid; e < m16 * 16; e += NT) {
+            const int c = e & 15;
+            B0[e] = (c < r && sig[c] > 0.0) ? B0[e] / sig[c] : 0.0;   // Um
+        }
+        __syncthreads();
+        mm_rows_gA<false>(gp(u.Mperp), sJ16, B0, B4, sI16, sJ16, sI);   // M_perp Um (sI x 16)
+        __syncthreads();
+        // X1b = M_perp Um,  X2b = Um Sigma
+        for (int e = tid; e < sI * R; e += NT) {
+            const int a = e / R, c = e - a * R;
+            gp(u.X1b)[e] = c < r ? B4[a * 16 + c] : 0.0;
+        }
+        for (int e = tid; e < sJ * R; e += NT) {
+            const int b = e / R, c = e - b * R;
+            gp(u.X2b)[e] = c < r ? B0[b * 16 + c] * sig[c] : 0.0;
+        }
     }
-    for (int e = tid; e < sJ * R; e += NT) {
-        const int b = e / R, c = e - b * R;
-        gp(u.X2)[e] = c < r ? __builtin_fma(B0[b * 16 + c], sig[c], gp(u.X2)[e]) : 0.0;
-    }
-    if (tid == 0 && fail) gp(u.flags)[0] |= 1;
+    UPHASE(15);
+    if (tid == 0 && fail) __hip_atomic_fetch_or(u.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename F>
@@ -1110,7 +1119,7 @@ hipError_t launch_ubsmall(const UBack* arr, int nb, int max_s16, int cg_max_it, 
     }
     const size_t lds = ubsmall_lds_bytes(max_s16);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    ubsmall_kernel<<<nb, 256, lds, s>>>(arr, cg_max_it, cg_tol);
+    ubsmall_kernel<<<2 * nb, 256, lds, s>>>(arr, cg_max_it, cg_tol);
     return hipGetLastError();
 }
 

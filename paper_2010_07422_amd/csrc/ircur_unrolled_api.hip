@@ -72,6 +72,8 @@ struct UHost {
     double* Tp = nullptr;
     double* X1 = nullptr;
     double* X2 = nullptr;
+    double* X1b = nullptr;
+    double* X2b = nullptr;
     double* P1 = nullptr;
     double* P2 = nullptr;
     std::vector<int32_t> Ih, Jh;   // host copies of the sets
@@ -277,6 +279,8 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             h.Tp = cv.take<double>((size_t)sJ * R);
             h.X1 = cv.take<double>((size_t)sI * R);
             h.X2 = cv.take<double>((size_t)sJ * R);
+            h.X1b = cv.take<double>((size_t)sI * R);
+            h.X2b = cv.take<double>((size_t)sJ * R);
             h.P1 = cv.take<double>((size_t)sI * R);
             h.P2 = cv.take<double>((size_t)sJ * R);
             if (pass == 0) {
@@ -417,7 +421,7 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             ub.partI = h.partI; ub.partJ = h.partJ; ub.partz = h.partz;
             ub.nwg_row = h.nwg_row; ub.nwg_col = h.nwg_col;
             ub.Wt = sa.W; ub.Q = sa.V; ub.Kc = sa.sigma; ub.TAd = sa.TAd; ub.M = M_k;
-            ub.Mperp = h.Mperp; ub.Wr = h.Wr; ub.Vr = h.Vr; ub.Tp = h.Tp; ub.X1 = h.X1; ub.X2 = h.X2;
+            ub.Mperp = h.Mperp; ub.Wr = h.Wr; ub.Vr = h.Vr; ub.Tp = h.Tp; ub.X1 = h.X1; ub.X2 = h.X2; ub.X1b = h.X1b; ub.X2b = h.X2b;
             ub.P1 = h.P1; ub.P2 = h.P2;
             ub.dz = u->dz_inst + e;
             ub.flags = u->flags + b;
