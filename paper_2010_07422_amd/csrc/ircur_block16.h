@@ -22,23 +22,10 @@ constexpr int XS = 17;
 constexpr int KMAX = 128;
 constexpr int TMAX = 32;
 
-// Lane permutations within rows of 16 lanes (DPP) applied to a double.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Sum over the 64 lanes of a wave, the same value in every lane: pairs, quads,
-// half rows and rows by DPP permutations (quad_perm [1,0,3,2], [2,3,0,1],
-// row_half_mirror, row_mirror), then the four row sums in row order.
+// Sum over the 64 lanes of a wave, the same value in every lane: the four
+// row sums (row16_sum) added in row order.
 __device__ __forceinline__ double wave_sum_dpp(double v) {
-    v += dpp_d<0xB1>(v);
-    v += dpp_d<0x4E>(v);
-    v += dpp_d<0x141>(v);
-    v += dpp_d<0x140>(v);
+    v = row16_sum(v);
     return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
 }
 

@@ -57,6 +57,26 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Lane permutations within rows of 16 lanes (DPP) applied to a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each row of 16 lanes, the same value in every lane of the row:
+// pairs, quads, half rows and rows by DPP permutations (quad_perm [1,0,3,2],
+// [2,3,0,1], row_half_mirror, row_mirror).
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return v;
+}
+
 // LDS view of a pointer into the kernel's shared memory: helpers that are not
 // inlined receive generic pointers, and generic (flat) accesses are slower
 // than LDS ones and hold up the waits for other memory results.

@@ -522,7 +522,9 @@ __device__ void jacobi16(double* K, double* Vm, int r) {
             for (int pp = 0; pp < r - 1; ++pp) {
                 for (int qq = pp + 1; qq < r; ++qq) {
                     const double kp = i < r ? K[i * 16 + pp] : 0.0, kq = i < r ? K[i * 16 + qq] : 0.0;
-                    const double al = wave_sum(kp * kp), be = wave_sum(kq * kq), ga = wave_sum(kp * kq);
+                    // column dot products over the r <= 16 rows (lanes 0-15), from lane 0
+                    const double al = readlane_d(row16_sum(kp * kp), 0), be = readlane_d(row16_sum(kq * kq), 0),
+                                 ga = readlane_d(row16_sum(kp * kq), 0);
                     if (!(fabs(ga) > 1e-15 * __builtin_sqrt(al * be))) continue;
                     ++rot;
                     const double zt = (be - al) / (2.0 * ga);
