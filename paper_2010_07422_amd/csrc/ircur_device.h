@@ -49,33 +49,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 // launch that follows it: sigma_{r+1} / sigma_r ~ sqrt(bx / lambda_min(Gy_rr))
 // with bx the extra columns' largest Rayleigh quotient (info->bx) and
 // lambda_min(Gy_rr) = 1 / lambda_max(Ly^-T Ly^-1) (T = Ly^-T, R x R), by eight
-// power steps on the first wave; sh: 64 doubles of LDS.
+// power steps on the first wave.  T and the vectors stay in LDS (sh: 288
+// doubles), so that the pass kernels keep their register budget.
 __device__ __forceinline__ void gap_estimate(const double* T, SvdInfo* info, int R, double* sh) {
     if (threadIdx.x >= 64) return;
     const int l = threadIdx.x;
+    double* Ts = sh;                           // R x R
+    double* vs = sh + 256;                     // 16
+    double* ws = sh + 272;                     // 16
+    for (int e = l; e < R * R; e += 64) Ts[e] = T[e];
     const double bx = info->bx;
     double gap = -1.0;
     if (bx >= 0.0) {
-        double tr[16], tc[16];                 // lane l < R: row l and column l of T = Ly^-T
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const bool in = l < R && k < R;
-            tr[k] = in ? T[l * R + k] : 0.0;
-            tc[k] = in ? T[k * R + l] : 0.0;
-        }
         double v = l < R ? 1.0 : 0.0, lam = 0.0;
         for (int s = 0; s < 8; ++s) {
-            sh[l] = v;
+            if (l < 16) vs[l] = v;
             __builtin_amdgcn_wave_barrier();
             double w = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) w = __builtin_fma(tc[k], sh[k], w);    // (T^T v)_l
-            __builtin_amdgcn_wave_barrier();
-            sh[l] = w;
+            if (l < R)
+                for (int k = 0; k < R; ++k) w = __builtin_fma(Ts[k * R + l], vs[k], w);   // (T^T v)_l
+            if (l < 16) ws[l] = w;
             __builtin_amdgcn_wave_barrier();
             double u = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) u = __builtin_fma(tr[k], sh[k], u);    // (T w)_l
+            if (l < R)
+                for (int k = 0; k < R; ++k) u = __builtin_fma(Ts[l * R + k], ws[k], u);   // (T w)_l
             __builtin_amdgcn_wave_barrier();
             const double nv = __builtin_sqrt(wave_sum(u * u));
             const double vv = __builtin_sqrt(wave_sum(v * v));

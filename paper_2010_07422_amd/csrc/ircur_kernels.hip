@@ -83,7 +83,7 @@ __global__ __launch_bounds__((64 * PassWaves<T, R>::value)) void pass_kernel(Pas
     if (a.st->stop) return;
     __shared__ F red[PassTree<T, F, R>::nred];
     __shared__ double redzd[PassTree<T, F, R>::nzd];
-    __shared__ double gsh[64];
+    __shared__ double gsh[288];
     // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so work item
     // w = xcd * per + slot gives each XCD a contiguous range of (side, column
     // tile, row block) items: neighbouring tiles, which share the cache lines at
