@@ -554,8 +554,8 @@ void ircur_unrolled_destroy(ircur_unrolled* u) {
     {
         DevState h{};
         if (hipMemcpy(&h, u->st, sizeof(DevState), hipMemcpyDeviceToHost) == hipSuccess) {
-            std::fprintf(stderr, "ubsmall phases of instance 0 (total us):");
-            for (int i = 9; i < 16; ++i) std::fprintf(stderr, " [%d] %.1f", i, (double)h.phase[i] * 0.01);
+            std::fprintf(stderr, "phases of instance 0 (total us; 0-8, 11: last forward's SVDs, 9-15: last backward's core adjoints):");
+            for (int i = 0; i < 16; ++i) std::fprintf(stderr, " [%d] %.1f", i, (double)h.phase[i] * 0.01);
             std::fprintf(stderr, "\n");
         }
     }
