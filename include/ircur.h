@@ -87,9 +87,10 @@ typedef struct {
     int32_t svd_max_it;  /* cap on the products with M^T M of one top-r SVD; 0: the
                             default, 256 in the one-launch SVD (r <= 16), 64
                             subspace iterations in the general one              */
-    int32_t svd_block;   /* subspace width p >= r of the top-r SVD; 0: default (16
-                            for r <= 16); a value other than 16 selects the
-                            general multi-launch SVD                            */
+    int32_t svd_block;   /* least subspace width of the top-r SVD (r <= svd_block
+                            <= 32); the width used is 16 or 32, the smaller one
+                            at least max(svd_block, padded r); 0: from r alone.
+                            Width 32 takes the general multi-launch SVD        */
     const double* zeta_sched; /* optional host array of max_iter thresholds (Algorithm
                             1, Phase I: any decreasing schedule zeta_{k+1}):
                             iteration k (0-based) thresholds with zeta_sched[k] in

@@ -613,9 +613,10 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
     c->p.zeta_sched = nullptr;               // (the copy above is the context's)
     const ircur_params& p = c->p;
     c->R = pad_rank(p.r);
-    // SVD: tile width P >= R; workgroups G the fewest of 8, 16, 32 whose LDS
-    // layout (M row block, subspace blocks) fits in 160 KiB.
-    const int P = c->R <= 16 ? 16 : 32;
+    // SVD: tile width P = 16 or 32, the smaller one at least max(R, svd_block);
+    // workgroups G the fewest of 8, 16, 32 whose LDS layout (M row block,
+    // subspace blocks) fits in 160 KiB.
+    const int P = std::max(c->R, (int)p.svd_block) <= 16 ? 16 : 32;
     int pb = P;
     size_t lds = 0;
     {
@@ -648,9 +649,8 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
         const int gc = (p.sI + 15) / 16;
-        // (a caller-chosen subspace width other than 16 takes the general SVD)
-        if (c->R <= 16 && gc <= ncu && p.sJ <= 512 && (p.svd_block == 0 || p.svd_block == 16) &&
-            csvd_lds_bytes(p.sJ, gc) <= 160 * 1024) {
+        // (16 columns: a width above 16 takes the general SVD)
+        if (P == 16 && gc <= ncu && p.sJ <= 512 && csvd_lds_bytes(p.sJ, gc) <= 160 * 1024) {
             c->csvd = true;
             c->Gc = gc;
             c->csvd_lds = csvd_lds_bytes(p.sJ, gc);

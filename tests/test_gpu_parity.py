@@ -23,7 +23,7 @@ def _ctx(torch, D, dtype, r, sI, sJ, zeta0, **kw):
 
 @pytest.mark.parametrize("n1,n2,r,s1,s2,k", [(700, 650, 4, 60, 55, 3), (257, 300, 1, 20, 31, 0),
                                               (1000, 1000, 5, 139, 139, 5), (500, 480, 12, 150, 140, 1)])
-def test_single_step_f64(n1, n2, r, s1, s2, k, alpha=0.1):
+def test_single_step_f64(n1, n2, r, s1, s2, k, alpha=0.1, svd_block=0):
     torch = require_gpu()
     p = synth.planted(n1, n2, r, alpha, seed=41 + k)
     I, J = sampler.draw_IJ(5, 0, n1, n2, s1, s2)
@@ -33,9 +33,9 @@ def test_single_step_f64(n1, n2, r, s1, s2, k, alpha=0.1):
         out = O.step(p.D, A, B, I, J, z0 * 0.7 ** kk, r)
         A, B = out["A1"], out["B1"]
     ref = O.step(p.D, A, B, I, J, z0 * 0.7 ** k, r)
-    print(f"case n1={n1} n2={n2} r={r} s=({s1},{s2}) k={k}", flush=True)
+    print(f"case n1={n1} n2={n2} r={r} s=({s1},{s2}) k={k} svd_block={svd_block}", flush=True)
     ctx, Dd = _ctx(torch, p.D, torch.float64, r, s1, s2, z0, eps=0.0, max_iter=k + 1, seed=5,
-                   resample=False)
+                   resample=False, svd_block=svd_block)
     if k > 0:
         ctx.set_factors(to_dev(torch, A.T, torch.float64), to_dev(torch, B, torch.float64), k)
     e = ctx.step(I, J)
@@ -53,6 +53,13 @@ def test_single_step_f64(n1, n2, r, s1, s2, k, alpha=0.1):
     assert O.factored_rel_diff(A1, B1, ref["A1"], ref["B1"]) <= 1e-11
     assert abs(e - ref["e"]) <= 1e-9 * ref["e"] + 1e-14      # e at rounding level: absolute
     ctx.close()
+
+
+def test_single_step_f64_caller_subspace_width():
+    """A caller-chosen subspace width above 16 (svd_block = 24 at r = 5: 32
+    columns) takes the general multi-launch SVD; same bar as the one-launch
+    SVD."""
+    test_single_step_f64(700, 650, 5, 60, 55, 2, svd_block=24)
 
 
 @pytest.mark.parametrize("alpha", [0.0, 0.02])
