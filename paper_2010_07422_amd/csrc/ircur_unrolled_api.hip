@@ -386,7 +386,10 @@ int ircur_unrolled_create(ircur_unrolled** out, const ircur_instance* inst, int3
             sa.MA = h.MA; sa.MB = h.MB; sa.sI = sI; sa.sJ = sJ; sa.r = u->r; sa.R = R; sa.p = 16;
             sa.G = u->G; sa.bs = 16 * (((sI + 15) / 16 + u->G - 1) / u->G);
             sa.max_it = 100;
-            sa.tol = dtype == IRCUR_F64 ? 1e-13 : 1e-9;
+            // FP32 data carry 24 significant bits: a subspace finer than about
+            // their rounding (1e-7) buys nothing, and every extra order costs
+            // ten power steps where sigma_{r+1} / sigma_r is near 0.9
+            sa.tol = dtype == IRCUR_F64 ? 1e-13 : 1e-7;
             sa.warm = (k == 0 ? 0 : 2) | (fd << 8);
             sa.salt = in.seed * 0x9E3779B97F4A7C15ull + (uint64_t)(k + 1) * 0xD1B54A32D192ED03ull;
             sa.prevV = nullptr; sa.prevV_out = nullptr;
@@ -556,6 +559,16 @@ void ircur_unrolled_destroy(ircur_unrolled* u) {
         if (hipMemcpy(&h, u->st, sizeof(DevState), hipMemcpyDeviceToHost) == hipSuccess) {
             std::fprintf(stderr, "phases of instance 0 (total us; 0-8, 11: last forward's SVDs, 9-15: last backward's core adjoints):");
             for (int i = 0; i < 16; ++i) std::fprintf(stderr, " [%d] %.1f", i, (double)h.phase[i] * 0.01);
+            std::fprintf(stderr, "\n");
+        }
+        // subspace iterations of the last forward's SVDs, per step (rows) and instance (columns)
+        for (int k = 0; k < u->K; ++k) {
+            std::fprintf(stderr, "svd iters k=%d:", k);
+            for (size_t b = 0; b < u->inst.size(); ++b) {
+                SvdInfo si{};
+                if (hipMemcpy(&si, u->inst[b].info + k, sizeof(SvdInfo), hipMemcpyDeviceToHost) == hipSuccess)
+                    std::fprintf(stderr, " %d", si.iters);
+            }
             std::fprintf(stderr, "\n");
         }
     }
