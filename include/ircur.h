@@ -80,7 +80,9 @@ typedef struct {
     double  eps;         /* stop when e_k <= eps (eps < 0: run max_iter iterations) */
     int32_t max_iter;    /* iteration cap, >= 1                                     */
     uint64_t seed;       /* index-sampler seed (SplitMix64 stream, see below)       */
-    double  svd_tol;     /* relative residual tolerance of the top-r SVD; 0: default
+    double  svd_tol;     /* residual tolerance of the top-r SVD (relative to the
+                            smallest wanted Rayleigh quotient in the one-launch
+                            SVD, to ||Q^T M^T M Q||_F in the general one); 0: default
                             (1e-13 for F64, 1e-9 for F32; for BF16
                             max(1e-7, 1e-2 e_k), e_k the stopping residual of the
                             iteration before, e_0 = 1)                              */
@@ -295,7 +297,9 @@ int ircur_get_info(ircur_ctx* ctx, int32_t* svd_iters, double* svd_resid,
  * iterations completed since ircur_init, ircur_reset, ircur_set_factors or
  * ircur_set_state (entry i is iteration k_0 + i + 1): subspace iterations
  * used, the Ritz estimate of sigma_{r+1} / sigma_r (the gap that decides
- * whether H_r is unique; -1 when the subspace block holds no column beyond r)
+ * whether H_r is unique; a lower bound once the wanted columns have
+ * converged, from the extra columns' largest Rayleigh quotient; -1 when the
+ * subspace block holds no column beyond r)
  * and the number of components kept by the pseudo-inverse rule.  Host arrays
  * of `cap` entries, any of them NULL; *n_out = entries written.
  * Synchronises.
