@@ -754,10 +754,10 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
         double s = 0.0, t = 0.0;
         for (int f = 0; f < R; ++f) {
             s = __builtin_fma(gp(u.Q)[b * R + f], Vk[f * 16 + c], s);
-            t = __builtin_fma(gp(u.Q)[b * R + f], gp(u.TAd)[f * R + c], t);
+            if (side == 1) t = __builtin_fma(gp(u.Q)[b * R + f], gp(u.TAd)[f * R + c], t);
         }
         gp(u.Vr)[e] = s;
-        gp(u.Tp)[e] = t;
+        if (side == 1) gp(u.Tp)[e] = t;
     }
     // Wbar = sum of row partials (sI x R) into B0, Tbar (sJ x R) into B1: one
     // thread per entry (a, c < R), the partials of 16 workgroups loaded
@@ -767,7 +767,8 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
         B1[e] = 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < (sI + sJ) * R; e += NT) {
+    // (the W side needs only Wbar, the V side only Tbar)
+    for (int e = tid + (side == 0 ? 0 : sI * R); e < (side == 0 ? sI * R : (sI + sJ) * R); e += NT) {
         const bool row = e < sI * R;
         const int ee = row ? e : e - sI * R;
         const int a = ee / R, c = ee - a * R;
@@ -825,13 +826,16 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
         const int c = tid >> 4, e = tid & 15;
         double s = 0.0, s0 = 0.0, s1 = 0.0;
         if (c < r && e < r) {
+            if (side == 0) {                    // (the W side's maps)
 #pragma unroll 8
-            for (int a = 0; a < sI; ++a) {
-                s = __builtin_fma(B2[a * 16 + c], B0[a * 16 + e], s);
-                s0 = __builtin_fma(B0[a * 16 + c], B2[a * 16 + e], s0);
+                for (int a = 0; a < sI; ++a) {
+                    s = __builtin_fma(B2[a * 16 + c], B0[a * 16 + e], s);
+                    s0 = __builtin_fma(B0[a * 16 + c], B2[a * 16 + e], s0);
+                }
+            } else {                            // (the V side's)
+#pragma unroll 8
+                for (int b = 0; b < sJ; ++b) s1 = __builtin_fma(B1[c * m16 + b], B3[b * 16 + e], s1);
             }
-#pragma unroll 8
-            for (int b = 0; b < sJ; ++b) s1 = __builtin_fma(B1[c * m16 + b], B3[b * 16 + e], s1);
         }
         Urr[tid] = s;
         K[tid] = s0;    // W_r^T P1t  (r x r)
@@ -886,7 +890,7 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
     }
     __syncthreads();
     // right-hand sides projected on the complements: P1t - W_r (W_r^T P1t) into
-    // B4 (W side), P2 - V_r (V_r^T P2) kept in global P2
+    // B4 (W side), P2 - V_r (V_r^T P2) kept in global P2 (V side)
     for (int e = tid; e < m16 * 16; e += NT) {
         const int a = e >> 4, c = e & 15;
         double w = 0.0, v = 0.0;
@@ -895,12 +899,12 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
             v = B3[e];
 #pragma unroll
             for (int f = 0; f < 16; ++f) {      // K, Vm are zero at and past r
-                if (a < sI) w = __builtin_fma(-B0[a * 16 + f], K[f * 16 + c], w);
-                if (a < sJ) v = __builtin_fma(-B1[f * m16 + a], Vm[f * 16 + c], v);
+                if (side == 0 && a < sI) w = __builtin_fma(-B0[a * 16 + f], K[f * 16 + c], w);
+                if (side == 1 && a < sJ) v = __builtin_fma(-B1[f * m16 + a], Vm[f * 16 + c], v);
             }
         }
         B4[e] = (a < sI) ? w : 0.0;
-        if (a < sJ && c < R) gp(u.P2)[a * R + c] = (c < r) ? v : 0.0;
+        if (side == 1 && a < sJ && c < R) gp(u.P2)[a * R + c] = (c < r) ? v : 0.0;
     }
     __syncthreads();
     UPHASE(12);
