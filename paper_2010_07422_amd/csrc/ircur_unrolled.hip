@@ -29,6 +29,7 @@
 #include "ircur_small.h"
 
 #include <stdint.h>
+#include <type_traits>
 
 namespace ircur {
 
@@ -50,14 +51,16 @@ __device__ __forceinline__ float round_down_f(double z) {
     return f;
 }
 
-// S = x g and its derivatives: g, dS/dx, dS/dzeta (tauz = tau_rel zeta).
+// S = x g and its derivatives: g, dS/dx, dS/dzeta, with tauz = tau_rel zeta
+// passed as the launch-uniform reciprocals itz = 1 / tauz and
+// itzz = 1 / (tauz zeta), so that an entry costs one division (that of g).
 template <typename F>
-__device__ __forceinline__ void gate_derivs(F x, F zeta, F tauz, F& g, F& dSdx, F& dSdz) {
+__device__ __forceinline__ void gate_derivs(F x, F zeta, F itz, F itzz, F& g, F& dSdx, F& dSdz) {
     const F ax = x < F(0) ? -x : x;
-    g = F(1) / (F(1) + exp_t(-(ax - zeta) / tauz));
+    g = F(1) / (F(1) + exp_t((zeta - ax) * itz));
     const F gg = g * (F(1) - g);
-    dSdx = g + ax * gg / tauz;
-    dSdz = -x * ax * gg / (tauz * zeta);
+    dSdx = g + ax * gg * itz;
+    dSdz = -x * ax * gg * itzz;
 }
 
 // ------------------------------------------------------------ forward ---
@@ -299,15 +302,20 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     __shared__ double zred[4];
     extern __shared__ __align__(16) unsigned char dyn[];
     const int b = find_inst(off, nb, blockIdx.x);
-    const UBack& u = arr[b];
+    // the table read through the constant space, so that the compiler takes
+    // its pointers as global ones (plain loads, not flat ones, whose waits
+    // would also hold up the LDS reads)
+    typedef const __attribute__((address_space(4))) UBack CUBack;
+    CUBack& u = ((CUBack*)arr)[b];
     const int local = blockIdx.x - off[b];
     const double zeta = *zk;
     const float zf = round_down_f(zeta);
     const F zF = (F)zeta;
-    const F tz = (F)(tau_rel * zeta);
+    const F itz = (F)(1.0 / (tau_rel * zeta));
+    const F itzz = (F)(1.0 / (tau_rel * zeta * zeta));
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool rowside = local < u.nwg_row;
     const int wg = rowside ? local : local - u.nwg_row;
     const int64_t n = rowside ? u.n2 : u.n1;
@@ -334,8 +342,10 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     F* qs = (F*)(dyn + (((size_t)s * sizeof(int) + 15) & ~(size_t)15));
     for (int e = tid; e < s; e += 256) rix[e] = rows[e];
     __syncthreads();
-    {
-        const int tot = s * stride;
+    // (the stride is R, 2R or 4R: each case with its own constant divisor)
+    auto fill = [&](auto kst) {
+        constexpr int ST = decltype(kst)::value;
+        const int tot = s * ST;
         for (int base = tid; base < tot; base += 256 * 8) {
             F v[8];
 #pragma unroll
@@ -343,7 +353,7 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                 const int e = base + q * 256;
                 F x = F(0);
                 if (e < tot) {
-                    const int a = e / stride, c = e - a * stride;
+                    const int a = e / ST, c = e - a * ST;
                     if (c < R) {
                         x = Qf[c * nq + rix[a]];
                     } else if (PH == 2) {
@@ -361,7 +371,10 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                 if (e < tot) qs[e] = v[q];
             }
         }
-    }
+    };
+    if (PH == 1) fill(std::integral_constant<int, R>{});
+    else if (rowside) fill(std::integral_constant<int, 4 * R>{});
+    else fill(std::integral_constant<int, 2 * R>{});
     __syncthreads();
 
     F p[R], pb[R];
@@ -416,7 +429,7 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                 const F x = d - dot;
                 F g, dSdx, dSdz;
                 if (GATE) {
-                    gate_derivs<F>(x, zF, tz, g, dSdx, dSdz);
+                    gate_derivs<F>(x, zF, itz, itzz, g, dSdx, dSdz);
                 } else {
                     g = above(x < F(0) ? -x : x, zeta, zf) ? F(1) : F(0);
                     dSdx = g;
