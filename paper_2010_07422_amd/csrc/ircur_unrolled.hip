@@ -261,38 +261,96 @@ constexpr int pow2_ceil(int v) { return v <= 1 ? 1 : 2 * pow2_ceil((v + 1) / 2);
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
 // Sum over the 64 lanes of V values per lane at once (V a power of two, at most
-// 64), by recursive halving: at distance d a lane keeps one half of its values
-// (the upper half if bit d of its lane id is set) and adds the partner's copy
-// of that half. After log2 V exchanges lane l holds the whole sum of value
-// l >> (6 - log2 V); plain butterfly steps finish the remaining distances.
-// V - 1 exchanges in all instead of 6 V; the summation tree is fixed.
-template <int CNT, int D, int V, typename F>
+// 64), by recursive halving: at level i a lane keeps one half of its values
+// (the upper half if lane bit halv_bit(i) is set) and adds its partner's copy
+// of that half, the partner differing in that bit and agreeing in the bits of
+// the earlier levels.  The first four levels (the largest) pair lanes within
+// a row of 16 by DPP moves on the vector ALU: row_mirror (l ^ 15),
+// row_half_mirror (l ^ 7), quad_perm (l ^ 2, l ^ 1); the last two take
+// l ^ 16 (swizzle inside 32 lanes) and l ^ 32 (permute through LDS).  The six
+// partner masks span all lane bits, so each final sum covers every lane.
+// After log2 V levels lane l holds the whole sum of value halving_index(l);
+// plain butterfly steps with the remaining partners finish smaller V.
+// Values whose index modulo RP is RL or more are zero padding: the levels
+// that split on the higher index bits leave them alone.  V - 1 exchanges at
+// most instead of 6 V; the summation tree is fixed.
+constexpr int halv_bit(int i) { return i < 4 ? 3 - i : i; }
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float swz16_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ __forceinline__ double swz16_f(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)u, 0x401F);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), 0x401F);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_any(double v) { return dpp_d<CTRL>(v); }
+template <int CTRL> __device__ __forceinline__ float dpp_any(float v) { return dpp_f<CTRL>(v); }
+
+// the partner's copy of v at level LV
+template <int LV, typename F>
+__device__ __forceinline__ F halv_partner(F v) {
+    if constexpr (LV == 0) return dpp_any<0x140>(v);          // row_mirror
+    else if constexpr (LV == 1) return dpp_any<0x141>(v);     // row_half_mirror
+    else if constexpr (LV == 2) return dpp_any<0x4E>(v);      // quad_perm [2,3,0,1]
+    else if constexpr (LV == 3) return dpp_any<0xB1>(v);      // quad_perm [1,0,3,2]
+    else if constexpr (LV == 4) return swz16_f(v);
+    else return __shfl_xor(v, 32, 64);
+}
+
+template <int CNT, int LV, int V, int RP, int RL, typename F>
 struct HalvingLevel {
     static __device__ __forceinline__ void run(F (&a)[V], int lane) {
         constexpr int h = CNT / 2;
-        const bool hi = (lane & D) != 0;
+        const bool hi = ((lane >> halv_bit(LV)) & 1) != 0;
 #pragma unroll
         for (int j = 0; j < h; ++j) {
+            if (h >= RP && (j % RP) >= RL) continue;       // padding: zero on both sides
             const F send = hi ? a[j] : a[j + h];
             const F keep = hi ? a[j + h] : a[j];
-            a[j] = keep + __shfl_xor(send, D, 64);
+            a[j] = keep + halv_partner<LV>(send);
         }
-        HalvingLevel<h, D / 2, V, F>::run(a, lane);
+        HalvingLevel<h, LV + 1, V, RP, RL, F>::run(a, lane);
     }
 };
-template <int D, int V, typename F>
-struct HalvingLevel<1, D, V, F> {
+template <int LV, int V, int RP, int RL, typename F>
+struct HalvingLevel<1, LV, V, RP, RL, F> {
     static __device__ __forceinline__ void run(F (&)[V], int) {}
 };
 
-template <int V, typename F>
+template <int LV, typename F>
+__device__ __forceinline__ F halving_tail(F v) {
+    if constexpr (LV >= 6) return v;
+    else return halving_tail<LV + 1>(v + halv_partner<LV>(v));
+}
+
+template <int V, int RP = 1, int RL = 1, typename F>
 __device__ __forceinline__ F halving_sum(F (&a)[V], int lane) {
     static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two <= 64");
-    HalvingLevel<V, 32, V, F>::run(a, lane);
-    F v = a[0];
+    HalvingLevel<V, 0, V, RP, RL, F>::run(a, lane);
+    return halving_tail<ilog2(V)>(a[0]);
+}
+
+// the value whose sum lane l holds after halving_sum<V>, and whether l is the
+// one lane that holds it (the lanes whose butterfly bits are all zero)
+template <int V>
+__device__ __forceinline__ int halving_index(int lane) {
+    int v = 0;
 #pragma unroll
-    for (int d = 32 >> ilog2(V); d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    for (int i = 0; i < ilog2(V); ++i) v = (v << 1) | ((lane >> halv_bit(i)) & 1);
     return v;
+}
+template <int V>
+__device__ __forceinline__ bool halving_writer(int lane) {
+    int m = 0;
+#pragma unroll
+    for (int i = ilog2(V); i < 6; ++i) m |= 1 << halv_bit(i);
+    return (lane & m) == 0;
 }
 
 template <typename T, typename F, int R, bool GATE, int PH>
@@ -468,7 +526,6 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
         constexpr int VMAX = sizeof(F) == 8 ? 32 : 64;
         constexpr int RG = U * RP <= VMAX ? U : VMAX / RP;
         constexpr int V = RG * RP;
-        constexpr int SH = 6 - ilog2(V);
 #pragma unroll
         for (int g0 = 0; g0 < U; g0 += RG) {
             F hv[V];
@@ -480,10 +537,10 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
                     else hv[i * RP + c] = F(0);
                 }
             }
-            const F sum = halving_sum<V>(hv, lane);
-            const int idx = lane >> SH;
+            const F sum = halving_sum<V, RP, R>(hv, lane);
+            const int idx = halving_index<V>(lane);
             const int row = a0 + g0 + idx / RP, c = idx % RP;
-            if ((lane & ((1 << SH) - 1)) == 0 && c < R && row < a_end)
+            if (halving_writer<V>(lane) && c < R && row < a_end)
                 part[((int64_t)wg * s + row) * R + c] = PH == 1 ? (double)sum : -(double)sum;
         }
     }
