@@ -32,6 +32,7 @@
 // [B_k[:, J_b] | Q[b, :] | Delta'[b, :]] with Delta'[b,:] = B_k[:,J_b] - Gamma' Q[b,:]^T,
 // Gamma' = B_k[:, J] Q; and the r x r maps Gamma, Gamma'^T and Ly^-T.
 #include "ircur_small.h"
+#include "ircur_block16.h"
 
 #include <stdint.h>
 
@@ -493,6 +494,45 @@ size_t svdl_lds_bytes(int sJ, int bs16, int G) {
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+// Cholesky QR of the 16 columns of X as in orthonormalise, with the
+// register factorisation chol16 (wave 0, no LDS round trip per elimination
+// step) in place of chol_inv; L^-T is staged in scr (row stride XS) and the
+// factor itself is not kept.  Same dead-column rule (pivot at or below 1e-14
+// times the largest diagonal entry), same passes and defect test.
+__device__ __forceinline__ void orthonormalise16(double* X, int m16, int rows_valid, int live, double* Gs, int* dead,
+                                                 double* scr, double* red, uint64_t salt) {
+    constexpr int P = 16;
+    int maxp = 4;
+    for (int pass = 0; pass < maxp; ++pass) {
+        mm_small<P, true, false>(X, P, X, P, Gs, m16, scr);
+        if (pass > 0) {
+            double dev = 0.0;
+            for (int e = threadIdx.x; e < P * P; e += NT) {
+                const int i = e / P, j = e - i * P;
+                if (i < live && j < live) dev = fmax(dev, fabs(Gs[e] - (i == j ? 1.0 : 0.0)));
+            }
+            for (int off = 32; off >= 1; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+            __syncthreads();
+            const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();
+            if (!(dmax > 1e-13)) break;
+        }
+        chol16(Gs, P, live, 1e-14, false, nullptr, scr, dead, nullptr, scr + 512);
+        mm_rows<P, false, false>(X, P, scr, XS, X, P, m16, P, rows_valid);
+        __syncthreads();
+        int nd = 0;
+        for (int j = 0; j < live; ++j) nd += dead[j];
+        if (nd > 0) {
+            for (int e = threadIdx.x; e < rows_valid * P; e += NT) {
+                const int c = e % P;
+                if (c < live && dead[c]) X[e] = rnd_unit(salt ^ (0x5bd1e995ull * (uint64_t)(pass + 1)), (uint64_t)e);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int G>
 __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
     constexpr int P = 16;
@@ -725,8 +765,7 @@ __device__ __forceinline__ void svdl_body(const SvdArgs& a, const int wg) {
         // all-gather: Q <- orth(Z)
         batched(sJ16 * P, [&](int e) { return e < sJ * P ? ld_dev(gp(a.Zr) + e) : 0.0; }, [&](int e, double v) { Q[e] = v; });
         __syncthreads();
-        orthonormalise<P>(Q, sJ16, sJ, r, Gs, Ls, Li, dead, scr, red,
-                          a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
+        orthonormalise16(Q, sJ16, sJ, r, Gs, dead, scr, red, a.salt ^ (0x2545F4914F6CDD1Dull * (uint64_t)(it + 1)));
         PHASE(7);
     }
 
