@@ -151,10 +151,9 @@ struct ircur_ctx {
     size_t esz = 0, fsz = 0;
     void* At[2] = {nullptr, nullptr};
     void* B[2] = {nullptr, nullptr};
-    int32_t* Idev = nullptr;
-    int32_t* Jdev = nullptr;
-    int32_t* Ipin = nullptr;
-    int32_t* Jpin = nullptr;
+    // index sets of the ring's slots, I then J in each slot (one upload per batch)
+    int32_t* IJdev = nullptr;
+    int32_t* IJpin = nullptr;
     double* M = nullptr;
     double* MA = nullptr;
     double* MB = nullptr;
@@ -293,14 +292,13 @@ int dalloc_bytes(ircur_ctx* c, void** ptr, size_t bytes) {
 }
 
 void free_all(ircur_ctx* c) {
-    void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->Idev, c->Jdev,
+    void* bufs[] = {c->Dt_own, c->At[0], c->At[1], c->B[0], c->B[1], c->IJdev,
                     c->M, c->MA, c->MB, c->Zp, c->Gp, c->prevV, c->W, c->V, c->sigma, c->rowI,
                     c->rowJ, c->GmI, c->GmJ, c->scaleJ, c->TAd, c->Abc, c->Bsc, c->Zr, c->rp, c->Xr, c->Icur, c->Jcur, c->nnz, c->alg2_buf, c->part_row, c->part_col, c->pacc, c->pzd, c->pcnt, c->st,
                     c->info, c->hist, c->rowIt, c->rowJt};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
-    if (c->Ipin) (void)hipHostFree(c->Ipin);
-    if (c->Jpin) (void)hipHostFree(c->Jpin);
+    if (c->IJpin) (void)hipHostFree(c->IJpin);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->ev_made)
@@ -531,15 +529,14 @@ int enqueue_chunk(ircur_ctx* c, int n, const int32_t* Igiven, const int32_t* Jgi
         HIPCHK(c, hipEventSynchronize(c->h2d[h]));
         c->h2d_pending[h] = false;
     }
-    const size_t strI = (size_t)p.sI + kIndexPad, strJ = (size_t)p.sJ + kIndexPad;
-    int32_t* Ibase = c->Ipin + (size_t)h * kChunk * strI;
-    int32_t* Jbase = c->Jpin + (size_t)h * kChunk * strJ;
-    int32_t* Idbase = c->Idev + (size_t)h * kChunk * strI;
-    int32_t* Jdbase = c->Jdev + (size_t)h * kChunk * strJ;
+    // slot j of the batch: I (sI entries and the padding), then J
+    const size_t strI = (size_t)p.sI + kIndexPad, strJ = (size_t)p.sJ + kIndexPad, strIJ = strI + strJ;
+    int32_t* hbase = c->IJpin + (size_t)h * kChunk * strIJ;
+    int32_t* dbase = c->IJdev + (size_t)h * kChunk * strIJ;
     for (int j = 0; j < n; ++j) {
         const int k = k0 + j;
-        int32_t* Ih = Ibase + (size_t)j * strI;
-        int32_t* Jh = Jbase + (size_t)j * strJ;
+        int32_t* Ih = hbase + (size_t)j * strIJ;
+        int32_t* Jh = Ih + strI;
         if (Igiven) {
             sorted_copy(Igiven, p.sI, Ih);
             sorted_copy(Jgiven, p.sJ, Jh);
@@ -555,14 +552,13 @@ int enqueue_chunk(ircur_ctx* c, int n, const int32_t* Igiven, const int32_t* Jgi
             std::copy(Jh, Jh + p.sJ, c->setsJ.begin() + (size_t)k * p.sJ);
         }
     }
-    HIPCHK(c, hipMemcpyAsync(Idbase, Ibase, sizeof(int32_t) * n * strI, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(Jdbase, Jbase, sizeof(int32_t) * n * strJ, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dbase, hbase, sizeof(int32_t) * n * strIJ, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(c->h2d[h], c->stream));
     c->h2d_pending[h] = true;
     c->batch += 1;
     for (int j = 0; j < n; ++j) {
-        const int rc = enqueue_iter(c, k0 + j, Idbase + (size_t)j * strI, Jdbase + (size_t)j * strJ,
-                                    Jbase + (size_t)j * strJ);
+        const int32_t* Id = dbase + (size_t)j * strIJ;
+        const int rc = enqueue_iter(c, k0 + j, Id, Id + strI, hbase + (size_t)j * strIJ + strI);
         if (rc) return rc;
         c->k_enq = k0 + j + 1;
     }
@@ -692,8 +688,7 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         TRY(dalloc_bytes(c, &c->At[i], R * p.n1 * c->fsz));
         TRY(dalloc_bytes(c, &c->B[i], R * p.n2 * c->fsz));
     }
-    TRY(dalloc(c, &c->Idev, (size_t)kRing * (p.sI + kIndexPad)));
-    TRY(dalloc(c, &c->Jdev, (size_t)kRing * (p.sJ + kIndexPad)));
+    TRY(dalloc(c, &c->IJdev, (size_t)kRing * (p.sI + p.sJ + 2 * kIndexPad)));
     if (hipEventCreateWithFlags(&c->h2d[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->h2d[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->snap_ev[0], hipEventDisableTiming) != hipSuccess ||
@@ -702,8 +697,8 @@ int ircur_init(ircur_ctx** out, const ircur_params* pin, const void* D_dev, cons
         delete c;
         return IRCUR_ERR_DEVICE;
     }
-    if (hipHostMalloc((void**)&c->Ipin, sizeof(int32_t) * kRing * (p.sI + kIndexPad), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->Jpin, sizeof(int32_t) * kRing * (p.sJ + kIndexPad), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void**)&c->IJpin, sizeof(int32_t) * kRing * (p.sI + p.sJ + 2 * kIndexPad),
+                      hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->snap_host, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
         free_all(c);
