@@ -706,28 +706,60 @@ __device__ int cg_solve(const gdouble* Mp, int sI16, int sJ16, int sI, int sJ, c
             mm_rows_gA<true>(Mp, sJ16, Tm, AP, sJ16, sI16, sJ);
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
-            const int c = e & 15;
-            AP[e] = (c < r && (e >> 4) < m) ? __builtin_fma(sig2[c], Pp[e], -AP[e]) : 0.0;
+        // The operator's result sig2 P - AP is formed where it is used, and
+        // each column sum is accumulated in the loop that produces its terms:
+        // thread t owns the entries e = t (mod 256), rows t >> 4 (mod 16) of
+        // column t & 15, so its partial sums run over the same entries in the
+        // same order as coldot16's.
+        const int cq = threadIdx.x & 15;
+        const double sg = sig2[cq];
+        const bool cl = cq < r;
+        // pap = sum over the rows of P (sig2 P - AP)
+        {
+            double sp = 0.0;
+            for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+                const double ap = (cl && (e >> 4) < m) ? __builtin_fma(sg, Pp[e], -AP[e]) : 0.0;
+                sp = __builtin_fma(Pp[e], ap, sp);
+            }
+            part[threadIdx.x] = sp;
+            __syncthreads();
+            if (threadIdx.x < 16) {
+                double t = 0.0;
+                for (int q = 0; q < 16; ++q) t += part[q * 16 + threadIdx.x];
+                pap[threadIdx.x] = t;
+            }
+            __syncthreads();
+        }
+        // X += al P, R -= al (sig2 P - AP), rn = column sums of R^2
+        {
+            const double al = (cl && pap[cq] > 0.0) ? rr[cq] / pap[cq] : 0.0;
+            double sr = 0.0;
+            for (int e = threadIdx.x; e < m16 * 16; e += NT) {
+                const double ap = (cl && (e >> 4) < m) ? __builtin_fma(sg, Pp[e], -AP[e]) : 0.0;
+                X[e] = __builtin_fma(al, Pp[e], X[e]);
+                const double rv = __builtin_fma(-al, ap, Rr[e]);
+                Rr[e] = rv;
+                sr = __builtin_fma(rv, rv, sr);
+            }
+            part[threadIdx.x] = sr;
+            __syncthreads();
+            if (threadIdx.x < 16) {
+                double t = 0.0;
+                for (int q = 0; q < 16; ++q) t += part[q * 16 + threadIdx.x];
+                rn[threadIdx.x] = t;
+            }
+            __syncthreads();
+        }
+        {
+            const double be = (cl && rr[cq] > 0.0) ? rn[cq] / rr[cq] : 0.0;
+            for (int e = threadIdx.x; e < m16 * 16; e += NT) Pp[e] = __builtin_fma(be, Pp[e], Rr[e]);
         }
         __syncthreads();
-        coldot16(Pp, AP, m16, part, pap);
-        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
-            const int c = e & 15;
-            const double al = (c < r && pap[c] > 0.0) ? rr[c] / pap[c] : 0.0;
-            X[e] = __builtin_fma(al, Pp[e], X[e]);
-            Rr[e] = __builtin_fma(-al, AP[e], Rr[e]);
-        }
-        __syncthreads();
-        coldot16(Rr, Rr, m16, part, rn);
-        for (int e = threadIdx.x; e < m16 * 16; e += NT) {
-            const int c = e & 15;
-            const double be = (c < r && rr[c] > 0.0) ? rn[c] / rr[c] : 0.0;
-            Pp[e] = __builtin_fma(be, Pp[e], Rr[e]);
-        }
-        __syncthreads();
-        if (threadIdx.x < 16) rr[threadIdx.x] = rn[threadIdx.x];
-        __syncthreads();
+        // the new residual norms become the current ones (the two buffers
+        // swap roles; every read of the old ones is behind the barrier above)
+        double* const t = rr;
+        rr = rn;
+        rn = t;
     }
     if (it >= max_it) fail = 1;
     (void)flag;
