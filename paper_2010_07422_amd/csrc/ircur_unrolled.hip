@@ -16,7 +16,8 @@
 // Reverse, per step k = K-1 .. 0, from Abar = dloss/dA_{k+1}, Bbar = dloss/dB_{k+1}:
 //   ubpass(1)  Wbar = R Bbar^T (sI x R) and Tbar = C^T Abar (sJ x R), recomputing
 //              the gathered rows and columns of this step from D
-//   ubsmall    adjoint of the core, one workgroup per instance: singular triplets
+//   ubsmall    adjoint of the core, two workgroups per instance (the W-side and
+//              the V-side solves run concurrently): singular triplets
 //              of H_r(M) from Kc, the projections P1 = V_r^T Ubar = Sigma U_k^T Wbar^T
 //              and P2 = Ubar W_r = Tbar U_k of the adjoint of U^+, resolvent solves
 //              (sigma_c^2 I - M_perp M_perp^T) x = P1 (and the M^T M side) by
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(256) void ubpass_kernel(const UBack* __restrict__ a
     }
 }
 
-// ---- adjoint of the core (one workgroup per instance) ---------------------
+// ---- adjoint of the core (two workgroups per instance, one per side) -----
 
 // Column dot products of two m x 16 LDS blocks (row stride 16), fixed order.
 __device__ void coldot16(const double* A, const double* B, int m, double* part, double* out) {
