@@ -1068,6 +1068,21 @@ __global__ __launch_bounds__(256) void ubsmall_kernel(const UBack* __restrict__ 
     if (tid == 0 && fail) __hip_atomic_fetch_or(u.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sum of nw partials p[0], p[stride], ..., added in index order; the loads
+// are issued 16 at a time so that they are in flight together.
+__device__ __forceinline__ double sum_strided(const double* __restrict__ p, int64_t stride, int nw) {
+    double s = 0.0;
+    for (int w0 = 0; w0 < nw; w0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = w0 + q < nw ? p[(int64_t)(w0 + q) * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (w0 + q < nw) s += v[q];
+    }
+    return s;
+}
+
 template <typename F>
 __global__ __launch_bounds__(256) void ubreduce_kernel(const UBack* __restrict__ arr, const int32_t* __restrict__ off,
                                                        int nb) {
@@ -1081,8 +1096,7 @@ __global__ __launch_bounds__(256) void ubreduce_kernel(const UBack* __restrict__
         const int e = local * 256 + threadIdx.x;
         if (e < u.sI * R) {
             const int a = e / R, c = e - a * R;
-            double s = 0.0;
-            for (int w = 0; w < u.nwg_row; ++w) s += u.partI[((int64_t)w * u.sI + a) * R + c];
+            const double s = sum_strided(u.partI + (int64_t)a * R + c, (int64_t)u.sI * R, u.nwg_row);
             F* A0 = (F*)u.Abar0;
             const int64_t idx = (int64_t)c * u.n1 + u.I[a];
             A0[idx] = (F)((double)A0[idx] + s);
@@ -1091,8 +1105,7 @@ __global__ __launch_bounds__(256) void ubreduce_kernel(const UBack* __restrict__
         const int e = (local - nI) * 256 + threadIdx.x;
         if (e < u.sJ * R) {
             const int bb = e / R, c = e - bb * R;
-            double s = 0.0;
-            for (int w = 0; w < u.nwg_col; ++w) s += u.partJ[((int64_t)w * u.sJ + bb) * R + c];
+            const double s = sum_strided(u.partJ + (int64_t)bb * R + c, (int64_t)u.sJ * R, u.nwg_col);
             F* B0 = (F*)u.Bbar0;
             const int64_t idx = (int64_t)c * u.n2 + u.J[bb];
             B0[idx] = (F)((double)B0[idx] + s);
